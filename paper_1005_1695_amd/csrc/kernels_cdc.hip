@@ -1,0 +1,483 @@
+// Content-defined chunking kernels.
+//
+// 1. Candidates.  Lane L owns bytes [4096 L, 4096 L + 4096) and rolls the
+//    48-byte window hash W_i = W_{i-1} B - in[i-48] B^48 + in[i] across them,
+//    after a 48-byte warm-up over the bytes just before its range.  A
+//    candidate is (W_i & mask) == 0.  Only W mod 2^k with 2^k >= mask
+//    matters (reduction mod 2^k is a ring homomorphism of Z/2^64), so masks
+//    of up to 32 bits roll in 32-bit registers and still decide exactly the
+//    same positions; wider masks roll in 64 bits.
+//    Output is a two-level bitmap: level 1 holds one bit per byte, stored
+//    only for nonzero 64-bit words; level 2 holds, per range, a 64-bit mask
+//    of which level-1 words are nonzero.  Plus a per-range candidate count.
+//
+// 2. Selection (the chunk rule is a sequential chain: each chunk start fixes
+//    the next).  The input is split into tiles of P >= max_len bytes.  Each
+//    tile's lane walks the chain speculatively from D bytes before its tile
+//    (D = 2P), records the starts that fall inside its tile and the first
+//    start past it (its exit).  Two chains that reach the same start agree
+//    from then on, so if the exit of tile t-1 equals the first start tile t
+//    recorded, tile t's starts are exact; tile 0 starts at 0 and is exact.
+//    A verification pass checks every tile in parallel; tiles that fail are
+//    re-walked from the true entry by a repair pass (rare on real data).
+//    A scan of per-tile counts then packs the starts into the ends array.
+#include "internal.h"
+
+namespace crystal {
+
+// ------------------------------------------------------------ candidates
+
+// Byte t (0..15) of a 16-byte vector.
+__device__ __forceinline__ uint32_t vbyte(const uint4 &v, int t)
+{
+    const uint32_t w = (t < 4) ? v.x : (t < 8) ? v.y : (t < 12) ? v.z : v.w;
+    return (w >> (8 * (t & 3))) & 0xffu;
+}
+
+__device__ __forceinline__ uint4 load_vec(const uint8_t *__restrict__ in, uint64_t pos,
+                                          uint64_t n)
+{
+    // pos is 16-byte aligned; a vector is read only if it holds an input byte.
+    if (pos < n)
+        return *reinterpret_cast<const uint4 *>(in + pos);
+    return make_uint4(0, 0, 0, 0);
+}
+
+// Roll 16 positions: `cin` holds the entering bytes, `cout` the bytes that
+// leave (48 positions earlier).  Returns the 16-bit candidate mask.
+template <typename WT>
+__device__ __forceinline__ uint32_t roll16(WT &w, const uint4 &cin, const uint4 &cout,
+                                          WT B, WT B48, WT M)
+{
+    uint32_t bits = 0;
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+        w = w * B + (WT)vbyte(cin, t) - (WT)vbyte(cout, t) * B48;
+        bits |= ((w & M) == 0 ? 1u : 0u) << t;
+    }
+    return bits;
+}
+
+template <typename WT>
+__device__ __forceinline__ void roll16_store(WT &w, const uint4 &cin, const uint4 &cout,
+                                             WT B, WT B48, uint64_t *__restrict__ dst,
+                                             uint64_t pos, uint64_t n)
+{
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+        w = w * B + (WT)vbyte(cin, t) - (WT)vbyte(cout, t) * B48;
+        const uint64_t i = pos + t;
+        if (i < n)
+            dst[i] = (i + 1 >= kWindow) ? (uint64_t)w : 0;
+    }
+}
+
+// MODE 0: candidate bitmap.  MODE 1: dump the 64-bit window hash per byte.
+template <typename WT, int MODE>
+__global__ __launch_bounds__(256) void k_cdc_roll(const uint8_t *__restrict__ in,
+                                                  uint64_t n, uint64_t base, uint64_t b48,
+                                                  uint64_t mask, uint64_t *__restrict__ l1,
+                                                  uint64_t *__restrict__ l2,
+                                                  uint32_t *__restrict__ cnt,
+                                                  uint64_t *__restrict__ wout)
+{
+    const uint64_t L = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t r0 = L * kRangeBytes;
+    if (r0 >= n)
+        return;
+    const uint64_t r1 = (r0 + kRangeBytes < n) ? r0 + kRangeBytes : n;
+    const WT B = (WT)base, B48 = (WT)b48, M = (WT)mask;
+    const uint4 zero = make_uint4(0, 0, 0, 0);
+
+    // Warm-up: the 48 bytes before r0 enter with nothing leaving, which
+    // leaves W equal to the window hash ending at r0 - 1.
+    WT w = 0;
+    uint4 p1 = zero, p2 = zero, p3 = zero;
+    if (r0 >= 48) {
+        p1 = load_vec(in, r0 - 48, n);
+        p2 = load_vec(in, r0 - 32, n);
+        p3 = load_vec(in, r0 - 16, n);
+        roll16<WT>(w, p1, zero, B, 0, M);
+        roll16<WT>(w, p2, zero, B, 0, M);
+        roll16<WT>(w, p3, zero, B, 0, M);
+    }
+
+    uint64_t l2bits = 0;
+    uint32_t count = 0;
+    const uint32_t ngroups = (uint32_t)((r1 - r0 + 63) >> 6);
+    uint4 c0 = load_vec(in, r0, n), c1 = load_vec(in, r0 + 16, n);
+    uint4 c2 = load_vec(in, r0 + 32, n), c3 = load_vec(in, r0 + 48, n);
+    for (uint32_t g = 0; g < ngroups; g++) {
+        const uint64_t pos = r0 + 64ull * g;
+        // prefetch the next 64 bytes while this group is rolled
+        uint4 n0 = zero, n1 = zero, n2 = zero, n3 = zero;
+        if (g + 1 < ngroups) {
+            n0 = load_vec(in, pos + 64, n);
+            n1 = load_vec(in, pos + 80, n);
+            n2 = load_vec(in, pos + 96, n);
+            n3 = load_vec(in, pos + 112, n);
+        }
+        if (MODE == 0) {
+            // leaving bytes of vector q are those of the vector 48 bytes back
+            uint64_t word = (uint64_t)roll16<WT>(w, c0, p1, B, B48, M);
+            word |= (uint64_t)roll16<WT>(w, c1, p2, B, B48, M) << 16;
+            word |= (uint64_t)roll16<WT>(w, c2, p3, B, B48, M) << 32;
+            word |= (uint64_t)roll16<WT>(w, c3, c0, B, B48, M) << 48;
+            // positions below 47 have no full window; positions >= r1 are
+            // outside the range
+            if (pos < 47)
+                word &= ~0ull << (47 - pos);
+            if (pos + 64 > r1)
+                word &= (r1 - pos >= 64) ? ~0ull : ((1ull << (r1 - pos)) - 1);
+            if (word) {
+                l1[pos >> 6] = word;
+                l2bits |= 1ull << g;
+                count += __popcll(word);
+            }
+        } else {
+            roll16_store<WT>(w, c0, p1, B, B48, wout, pos, r1);
+            roll16_store<WT>(w, c1, p2, B, B48, wout, pos + 16, r1);
+            roll16_store<WT>(w, c2, p3, B, B48, wout, pos + 32, r1);
+            roll16_store<WT>(w, c3, c0, B, B48, wout, pos + 48, r1);
+        }
+        p1 = c1;
+        p2 = c2;
+        p3 = c3;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    if (MODE == 0) {
+        l2[L] = l2bits;
+        cnt[L] = count;
+    }
+}
+
+// ------------------------------------------------------------------ scans
+// Exclusive scan of n u32 counts into u64 offsets by one workgroup of 1024
+// threads; *total receives the sum.  Adequate for the per-range and
+// per-tile count arrays (<= a few hundred thousand entries).
+__global__ __launch_bounds__(1024) void k_scan_u32(const uint32_t *__restrict__ in,
+                                                   uint64_t n, uint64_t *__restrict__ out,
+                                                   uint64_t *__restrict__ total)
+{
+    __shared__ uint64_t wsum[16];
+    __shared__ uint64_t carry_s;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid == 0)
+        carry_s = 0;
+    __syncthreads();
+    for (uint64_t base = 0; base < n; base += 1024) {
+        const uint64_t i = base + tid;
+        const uint64_t v = i < n ? in[i] : 0;
+        // inclusive wave scan
+        uint64_t x = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            uint64_t y = __shfl_up(x, d, 64);
+            if (lane >= (uint32_t)d)
+                x += y;
+        }
+        if (lane == 63)
+            wsum[wv] = x;
+        __syncthreads();
+        uint64_t before = carry_s;
+        for (uint32_t k = 0; k < wv; k++)
+            before += wsum[k];
+        if (i < n)
+            out[i] = before + x - v;
+        __syncthreads();
+        if (tid == 1023)
+            carry_s = before + x;
+        __syncthreads();
+    }
+    if (tid == 0)
+        *total = carry_s;
+}
+
+// Candidate list from the bitmap: range L writes its positions at its scanned
+// offset.  Positions beyond cap are dropped (the count is still exact).
+__global__ __launch_bounds__(256) void k_cdc_compact(const uint64_t *__restrict__ l1,
+                                                     const uint64_t *__restrict__ l2,
+                                                     const uint64_t *__restrict__ rscan,
+                                                     uint64_t n_ranges,
+                                                     uint64_t *__restrict__ cand,
+                                                     uint64_t cap)
+{
+    const uint64_t L = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L >= n_ranges)
+        return;
+    uint64_t o = rscan[L];
+    uint64_t m = l2[L];
+    while (m) {
+        const uint32_t g = __builtin_ctzll(m);
+        m &= m - 1;
+        uint64_t bits = l1[L * 64 + g];
+        while (bits) {
+            const uint32_t b = __builtin_ctzll(bits);
+            bits &= bits - 1;
+            if (o < cap)
+                cand[o] = L * kRangeBytes + 64ull * g + b;
+            o++;
+        }
+    }
+}
+
+// -------------------------------------------------------------- selection
+
+struct SelArgs {
+    const uint64_t *l1, *l2;
+    uint64_t n, min_len, max_len, tile_bytes, warm_bytes;
+    uint32_t n_tiles, tile_cap;
+    uint64_t *exit_, *first;
+    uint32_t *tcnt;
+    uint64_t *starts;
+    uint32_t *flags;
+    uint32_t *bad; // [0] = count of tiles failing verification, [1] = overflow
+};
+
+constexpr uint64_t kNone = ~0ull;
+
+// First candidate position c with lo <= c <= hi, or kNone.
+__device__ __forceinline__ uint64_t first_cand(const SelArgs &a, uint64_t lo, uint64_t hi)
+{
+    if (lo > hi)
+        return kNone;
+    const uint64_t wlo = lo >> 6, whi = hi >> 6;
+    uint64_t w = wlo;
+    while (w <= whi) {
+        const uint64_t R = w >> 6;
+        const uint64_t m = a.l2[R] & (~0ull << (w & 63));
+        if (m == 0) {
+            w = (R + 1) << 6;
+            continue;
+        }
+        const uint64_t g = (R << 6) + __builtin_ctzll(m);
+        if (g > whi)
+            return kNone;
+        uint64_t bits = a.l1[g];
+        if (g == wlo)
+            bits &= ~0ull << (lo & 63);
+        if (bits) {
+            const uint64_t c = (g << 6) + __builtin_ctzll(bits);
+            return c <= hi ? c : kNone;
+        }
+        w = g + 1;
+    }
+    return kNone;
+}
+
+// Start of the chunk after the one starting at s (< n): the first candidate
+// i with i+1-s >= min_len, unless the length reaches max_len first; the
+// input end if neither happens.
+__device__ __forceinline__ uint64_t next_start(const SelArgs &a, uint64_t s)
+{
+    const uint64_t lo = s + a.min_len - 1;
+    uint64_t hi = s + a.max_len - 1;
+    if (hi > a.n - 1)
+        hi = a.n - 1;
+    const uint64_t c = first_cand(a, lo, hi);
+    if (c != kNone)
+        return c + 1;
+    if (s + a.max_len <= a.n)
+        return s + a.max_len;
+    return a.n;
+}
+
+// Walk from `s` recording the starts inside tile t; returns the exit.
+__device__ uint64_t walk_tile(const SelArgs &a, uint32_t t, uint64_t s)
+{
+    const uint64_t lt = (uint64_t)t * a.tile_bytes;
+    uint64_t lt1 = lt + a.tile_bytes;
+    if (lt1 > a.n)
+        lt1 = a.n;
+    uint32_t c = 0;
+    uint64_t first = kNone;
+    uint64_t *dst = a.starts + (uint64_t)t * a.tile_cap;
+    while (s < lt1) {
+        if (s >= lt) {
+            if (c < a.tile_cap)
+                dst[c] = s;
+            else
+                a.bad[1] = 1; // cannot happen when tile_cap >= ceil(P/min)
+            if (c == 0)
+                first = s;
+            c++;
+        }
+        s = next_start(a, s);
+    }
+    a.first[t] = (c ? first : s);
+    a.tcnt[t] = c;
+    a.exit_[t] = s;
+    return s;
+}
+
+__global__ __launch_bounds__(64) void k_sel_walk(SelArgs a)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n_tiles)
+        return;
+    const uint64_t lt = (uint64_t)t * a.tile_bytes;
+    const uint64_t s = lt > a.warm_bytes ? lt - a.warm_bytes : 0;
+    walk_tile(a, t, s);
+}
+
+__global__ __launch_bounds__(256) void k_sel_verify(SelArgs a)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0 || t >= a.n_tiles)
+        return;
+    const uint32_t badt = a.exit_[t - 1] != a.first[t];
+    a.flags[t] = badt;
+    if (badt)
+        atomicAdd(&a.bad[0], 1u);
+}
+
+// One thread re-walks, in order, every tile whose entry disagrees with the
+// true chain, then re-checks the next tile whenever a repaired exit moved.
+__global__ void k_sel_repair(SelArgs a)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0)
+        return;
+    if (a.bad[0] == 0)
+        return;
+    for (uint32_t t = 1; t < a.n_tiles; t++) {
+        const uint64_t entry = a.exit_[t - 1];
+        if (entry == a.first[t])
+            continue;
+        walk_tile(a, t, entry);
+    }
+}
+
+// Pack the starts: global start index k = toff[t] + i; start k >= 1 is end
+// k-1; the last end is n.
+__global__ __launch_bounds__(64) void k_sel_emit(SelArgs a, const uint64_t *__restrict__ toff,
+                                                 const uint64_t *__restrict__ total,
+                                                 uint64_t *__restrict__ n_chunks,
+                                                 uint64_t *__restrict__ ends, uint64_t cap)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n_tiles)
+        return;
+    const uint64_t o = toff[t];
+    const uint32_t c = a.tcnt[t];
+    const uint64_t *src = a.starts + (uint64_t)t * a.tile_cap;
+    for (uint32_t i = 0; i < c; i++) {
+        const uint64_t k = o + i;
+        if (k >= 1 && k - 1 < cap)
+            ends[k - 1] = src[i];
+    }
+    if (t == a.n_tiles - 1) {
+        const uint64_t m = *total; // number of chunk starts = number of chunks
+        if (m >= 1 && m - 1 < cap)
+            ends[m - 1] = a.n;
+        *n_chunks = m;
+    }
+}
+
+__global__ void k_store_zero_u64(uint64_t *p)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *p = 0;
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline uint32_t nblk(uint64_t n, uint32_t b) { return (uint32_t)((n + b - 1) / b); }
+
+hipError_t launch_cdc_candidates(const uint8_t *in, const CdcGeom &g, const CdcParams &p,
+                                 uint8_t *ws, hipStream_t s)
+{
+    if (g.n == 0)
+        return hipSuccess;
+    uint64_t *l1 = reinterpret_cast<uint64_t *>(ws + g.off_l1);
+    uint64_t *l2 = reinterpret_cast<uint64_t *>(ws + g.off_l2);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + g.off_cnt);
+    const dim3 grid(nblk(g.n_ranges, 256)), block(256);
+    if (p.mask_bits <= 32)
+        hipLaunchKernelGGL((k_cdc_roll<uint32_t, 0>), grid, block, 0, s, in, g.n, p.base,
+                           p.b48, p.mask, l1, l2, cnt, (uint64_t *)nullptr);
+    else
+        hipLaunchKernelGGL((k_cdc_roll<uint64_t, 0>), grid, block, 0, s, in, g.n, p.base,
+                           p.b48, p.mask, l1, l2, cnt, (uint64_t *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_cdc_compact(const CdcGeom &g, uint8_t *ws, uint64_t *d_count,
+                              uint64_t *d_cand, uint64_t cap, hipStream_t s)
+{
+    if (g.n == 0) {
+        hipLaunchKernelGGL(k_store_zero_u64, dim3(1), dim3(64), 0, s, d_count);
+        return hipGetLastError();
+    }
+    uint64_t *l1 = reinterpret_cast<uint64_t *>(ws + g.off_l1);
+    uint64_t *l2 = reinterpret_cast<uint64_t *>(ws + g.off_l2);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + g.off_cnt);
+    uint64_t *rscan = reinterpret_cast<uint64_t *>(ws + g.off_rscan);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, cnt, g.n_ranges, rscan, d_count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || d_cand == nullptr)
+        return e;
+    hipLaunchKernelGGL(k_cdc_compact, dim3(nblk(g.n_ranges, 256)), dim3(256), 0, s, l1, l2,
+                       rscan, g.n_ranges, d_cand, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_cdc_select(const CdcGeom &g, const CdcParams &p, uint8_t *ws,
+                             uint64_t *d_n_chunks, uint64_t *d_ends, uint64_t cap,
+                             hipStream_t s)
+{
+    if (g.n == 0) {
+        hipLaunchKernelGGL(k_store_zero_u64, dim3(1), dim3(64), 0, s, d_n_chunks);
+        return hipGetLastError();
+    }
+    SelArgs a;
+    a.l1 = reinterpret_cast<const uint64_t *>(ws + g.off_l1);
+    a.l2 = reinterpret_cast<const uint64_t *>(ws + g.off_l2);
+    a.n = g.n;
+    a.min_len = p.min_len;
+    a.max_len = p.max_len;
+    a.tile_bytes = g.tile_bytes;
+    a.warm_bytes = g.warm_bytes;
+    a.n_tiles = g.n_tiles;
+    a.tile_cap = g.tile_cap;
+    a.exit_ = reinterpret_cast<uint64_t *>(ws + g.off_exit);
+    a.first = reinterpret_cast<uint64_t *>(ws + g.off_first);
+    a.tcnt = reinterpret_cast<uint32_t *>(ws + g.off_tcnt);
+    a.starts = reinterpret_cast<uint64_t *>(ws + g.off_starts);
+    a.flags = reinterpret_cast<uint32_t *>(ws + g.off_flags);
+    a.bad = reinterpret_cast<uint32_t *>(ws + g.off_bad);
+    uint64_t *toff = reinterpret_cast<uint64_t *>(ws + g.off_toff);
+    uint64_t *total = reinterpret_cast<uint64_t *>(ws + g.off_misc);
+    hipError_t e;
+    e = launch_zero_u32(a.bad, 2u, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_sel_walk, dim3(nblk(g.n_tiles, 64)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_sel_verify, dim3(nblk(g.n_tiles, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sel_repair, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, a.tcnt, (uint64_t)g.n_tiles,
+                       toff, total);
+    hipLaunchKernelGGL(k_sel_emit, dim3(nblk(g.n_tiles, 64)), dim3(64), 0, s, a, toff, total,
+                       d_n_chunks, d_ends, cap);
+    e = hipGetLastError();
+    return e;
+}
+
+hipError_t launch_window_hash(const uint8_t *in, uint64_t n, uint64_t base, uint64_t *w,
+                              hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    uint64_t b48 = 1;
+    for (int i = 0; i < 48; i++)
+        b48 *= base;
+    const uint64_t nr = (n + kRangeBytes - 1) / kRangeBytes;
+    hipLaunchKernelGGL((k_cdc_roll<uint64_t, 1>), dim3(nblk(nr, 256)), dim3(256), 0, s, in, n,
+                       base, b48, ~0ull, (uint64_t *)nullptr, (uint64_t *)nullptr,
+                       (uint32_t *)nullptr, w);
+    return hipGetLastError();
+}
+
+} // namespace crystal

@@ -1,0 +1,262 @@
+// MD5 kernels: per-segment direct hashing, digest-of-digests roots, whole
+// buffers, batched small buffers (plain and persistent) and per-chunk
+// digests.  One lane hashes one message; see md5_device.h.
+#include "internal.h"
+#include "md5_device.h"
+
+namespace crystal {
+
+// Lane s hashes segment s of the launch.  Multi-job launches locate the job
+// by binary search in the segment prefix table (largest j with
+// seg_base[j] <= s), which also skips empty jobs.
+__global__ __launch_bounds__(256) void k_md5_segments(const uint8_t *__restrict__ in,
+                                                      JobTable jt, uint32_t seg_bytes,
+                                                      uint64_t n_segments,
+                                                      uint8_t *__restrict__ dig)
+{
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_segments)
+        return;
+    uint64_t off = 0, len = jt.single_len, local = s;
+    if (jt.n_jobs) {
+        uint32_t lo = 0, hi = jt.n_jobs;
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (jt.seg_base[mid] <= s)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        off = jt.off[lo];
+        len = jt.len[lo];
+        local = s - jt.seg_base[lo];
+    }
+    const uint64_t start = local * seg_bytes;
+    const uint64_t rem = len - start;
+    const uint64_t n = rem < seg_bytes ? rem : seg_bytes;
+    const uint8_t *p = in + off + start;
+    uint32_t st[4];
+    if (((uintptr_t)p & 15) == 0)
+        md5_message_a16(p, n, st);
+    else
+        md5_message_any(p, n, st);
+    md5_store(dig + 16 * s, st);
+}
+
+// Lane j computes the root of job j: MD5 over its segment digests, which are
+// contiguous and 16-byte aligned in the digest array.
+__global__ __launch_bounds__(64) void k_md5_roots(const uint8_t *__restrict__ dig,
+                                                  JobTable jt, uint32_t seg_bytes,
+                                                  uint8_t *__restrict__ roots)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nj = jt.n_jobs ? jt.n_jobs : 1;
+    if (j >= nj)
+        return;
+    uint64_t b0 = 0, nseg;
+    if (jt.n_jobs) {
+        b0 = jt.seg_base[j];
+        nseg = jt.seg_base[j + 1] - b0;
+    } else {
+        nseg = (jt.single_len + seg_bytes - 1) / seg_bytes;
+    }
+    uint32_t st[4];
+    md5_message_a16(dig + 16 * b0, 16 * nseg, st);
+    md5_store(roots + 16 * j, st);
+}
+
+__global__ __launch_bounds__(64) void k_md5_whole(const uint8_t *__restrict__ in,
+                                                  uint64_t n, uint8_t *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    uint32_t st[4];
+    if (((uintptr_t)in & 15) == 0)
+        md5_message_a16(in, n, st);
+    else
+        md5_message_any(in, n, st);
+    md5_store(out, st);
+}
+
+__device__ __forceinline__ void md5_one_buffer(const uint8_t *__restrict__ arena,
+                                               const uint64_t *__restrict__ off,
+                                               const uint32_t *__restrict__ len,
+                                               uint64_t m, uint8_t *__restrict__ out)
+{
+    const uint8_t *p = arena + off[m];
+    const uint64_t l = len[m];
+    uint32_t st[4];
+    if (((uintptr_t)p & 15) == 0)
+        md5_message_a16(p, l, st);
+    else
+        md5_message_any(p, l, st);
+    md5_store(out + 16 * m, st);
+}
+
+// Grid-stride batch: lane i takes buffers order[i], order[i + G], ...
+__global__ void k_md5_batch(const uint8_t *__restrict__ arena,
+                            const uint64_t *__restrict__ off,
+                            const uint32_t *__restrict__ len,
+                            const uint32_t *__restrict__ order, uint64_t n,
+                            uint8_t *__restrict__ out)
+{
+    const uint64_t G = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += G) {
+        const uint64_t m = order ? order[i] : i;
+        md5_one_buffer(arena, off, len, m, out);
+    }
+}
+
+// Persistent batch: each wave repeatedly takes the next grab*64 entries of
+// the (longest-first) order from a global counter, so waves that drew short
+// buffers come back for more.  Every wave leaves once the counter passes n.
+__global__ void k_md5_batch_persistent(const uint8_t *__restrict__ arena,
+                                       const uint64_t *__restrict__ off,
+                                       const uint32_t *__restrict__ len,
+                                       const uint32_t *__restrict__ order,
+                                       uint64_t n, uint8_t *__restrict__ out,
+                                       uint32_t *__restrict__ counter, uint32_t grab)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t span = grab * 64u;
+    for (;;) {
+        uint32_t base = 0;
+        if (lane == 0)
+            base = atomicAdd(counter, span);
+        base = __shfl(base, 0, 64);
+        if ((uint64_t)base >= n)
+            break;
+        for (uint32_t k = 0; k < grab; k++) {
+            const uint64_t i = (uint64_t)base + 64u * k + lane;
+            if (i < n) {
+                const uint64_t m = order ? order[i] : i;
+                md5_one_buffer(arena, off, len, m, out);
+            }
+        }
+    }
+}
+
+__global__ void k_zero_u32(uint32_t *p, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0;
+}
+
+// Lane k hashes chunk [ends[k-1], ends[k]); chunk starts are arbitrary byte
+// offsets, so the realigning loader is used.  With dig == nullptr the
+// digests go right after the ends array (ends + n_chunks), the packed job
+// output layout; that address is only 8-byte aligned.
+__global__ __launch_bounds__(256) void k_md5_chunks(const uint8_t *__restrict__ in,
+                                                    const uint64_t *__restrict__ ends,
+                                                    const uint64_t *__restrict__ n_chunks,
+                                                    uint64_t cap,
+                                                    uint8_t *__restrict__ dig)
+{
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t nc = *n_chunks;
+    if (nc > cap)
+        nc = cap;
+    if (k >= nc)
+        return;
+    const uint64_t lo = k ? ends[k - 1] : 0;
+    const uint64_t hi = ends[k];
+    uint32_t st[4];
+    md5_message_any(in + lo, hi - lo, st);
+    if (dig) {
+        md5_store(dig + 16 * k, st);
+    } else {
+        uint64_t *q = const_cast<uint64_t *>(ends) + nc + 2 * k;
+        q[0] = (uint64_t)st[0] | ((uint64_t)st[1] << 32);
+        q[1] = (uint64_t)st[2] | ((uint64_t)st[3] << 32);
+    }
+}
+
+__global__ void k_nop() {}
+
+// ------------------------------------------------------------------ launch
+
+static inline uint32_t blocks_for(uint64_t n, uint32_t b)
+{
+    return (uint32_t)((n + b - 1) / b);
+}
+
+hipError_t launch_md5_segments(const uint8_t *in, const JobTable &jt,
+                               uint32_t seg_bytes, uint64_t n_segments,
+                               uint8_t *seg_digests, hipStream_t s)
+{
+    if (n_segments == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_md5_segments, dim3(blocks_for(n_segments, 256)), dim3(256),
+                       0, s, in, jt, seg_bytes, n_segments, seg_digests);
+    return hipGetLastError();
+}
+
+hipError_t launch_md5_roots(const uint8_t *seg_digests, const JobTable &jt,
+                            uint32_t seg_bytes, uint8_t *roots, hipStream_t s)
+{
+    const uint32_t nj = jt.n_jobs ? jt.n_jobs : 1;
+    hipLaunchKernelGGL(k_md5_roots, dim3(blocks_for(nj, 64)), dim3(64), 0, s,
+                       seg_digests, jt, seg_bytes, roots);
+    return hipGetLastError();
+}
+
+hipError_t launch_md5_whole(const uint8_t *in, uint64_t n, uint8_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_md5_whole, dim3(1), dim3(64), 0, s, in, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_md5_batch(const uint8_t *arena, const uint64_t *off,
+                            const uint32_t *len, const uint32_t *order,
+                            uint64_t n, uint8_t *out, uint32_t block,
+                            uint32_t grid, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    if (grid == 0)
+        grid = blocks_for(n, block);
+    hipLaunchKernelGGL(k_md5_batch, dim3(grid), dim3(block), 0, s, arena, off, len,
+                       order, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_md5_batch_persistent(const uint8_t *arena, const uint64_t *off,
+                                       const uint32_t *len, const uint32_t *order,
+                                       uint64_t n, uint8_t *out, uint32_t *counter,
+                                       uint32_t grab, uint32_t block,
+                                       uint32_t grid, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_md5_batch_persistent, dim3(grid), dim3(block), 0, s, arena,
+                       off, len, order, n, out, counter, grab);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_md5_chunks(const uint8_t *in, const uint64_t *ends,
+                             const uint64_t *n_chunks, uint64_t cap,
+                             uint8_t *digests, hipStream_t s)
+{
+    if (cap == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_md5_chunks, dim3(blocks_for(cap, 256)), dim3(256), 0, s,
+                       in, ends, n_chunks, cap, digests);
+    return hipGetLastError();
+}
+
+hipError_t launch_nop(hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nop, dim3(1), dim3(64), 0, s);
+    return hipGetLastError();
+}
+
+} // namespace crystal

@@ -1,0 +1,742 @@
+// Job layer (the CrystalGPU design of Sec. 4.2 on one MI355X).
+//
+// State machine per job, as in the paper's three queues (Sec. 4.2): the
+// caller takes buffers from the idle pool (crystal_buffer_acquire), submits a
+// job to the outstanding queue, and a master thread dispatches it.  Here:
+//   - one dispatcher thread pops the outstanding queue in FIFO order and
+//     admits the head job only when the device slab has room for its input,
+//     output and scratch (first fit) and fewer than max_in_flight jobs are
+//     running; it then enqueues copy-in, kernels, copy-out and an event on
+//     the least-loaded of the library's streams, so consecutive jobs overlap
+//     copy and compute (the three-stage pipeline of Fig. 4);
+//   - one completion thread per stream waits for that stream's jobs in order
+//     (a stream completes in order), returns their device memory, runs the
+//     callback and wakes waiters -- the asynchronous notification the paper
+//     adds on top of a runtime that only offers polling (Sec. 4.1).
+// Buffers are carved from one pinned host slab so copies never go through a
+// driver staging buffer (Sec. 2.1, Sec. 3).
+#include <algorithm>
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <string.h>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+struct crystal_buf {
+    void *host;
+    size_t size;
+    size_t pool_off, pool_len; // region of the host slab (pooled buffers)
+    bool pooled;
+    std::atomic<int> refs;
+};
+
+namespace crystal {
+
+static inline size_t al(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// First-fit allocator over offsets [0, size) with coalescing free list.
+class RangeAlloc {
+  public:
+    void reset(size_t size)
+    {
+        free_.clear();
+        if (size)
+            free_[0] = size;
+        size_ = free_bytes_ = min_free_ = size;
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes)
+                continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes, o2 = it->first + bytes;
+            free_.erase(it);
+            if (rest)
+                free_[o2] = rest;
+            free_bytes_ -= bytes;
+            min_free_ = std::min(min_free_, free_bytes_);
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        size_t o = off, len = bytes;
+        auto next = free_.lower_bound(off);
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                o = prev->first;
+                len += prev->second;
+                free_.erase(prev);
+            }
+        }
+        if (next != free_.end() && off + bytes == next->first) {
+            len += next->second;
+            free_.erase(next);
+        }
+        free_[o] = len;
+        free_bytes_ += bytes;
+    }
+    size_t size() const { return size_; }
+    size_t free_bytes() const { return free_bytes_; }
+    size_t min_free() const { return min_free_; }
+
+  private:
+    std::map<size_t, size_t> free_;
+    size_t size_ = 0, free_bytes_ = 0, min_free_ = 0;
+};
+
+struct Job {
+    crystal_task *t;
+    int kernel;
+    crystal_buf *in, *out;
+    size_t n;
+    size_t need, dev_off;
+    size_t in_region;
+    int stream;
+    hipEvent_t ev;
+    uint32_t seg_bytes;
+    CdcParams cp;
+    CdcGeom g;
+    uint64_t cap;
+    size_t d2h;
+};
+
+// Device bytes a job needs and the layout inside its region:
+// [input | output | scratch], each 256-byte aligned.
+struct JobPlan {
+    size_t in_region, out_region, ws_region, d2h;
+};
+
+static bool plan_job(int kernel, size_t n, const void *params, Job *j, JobPlan *p,
+                     const char **why)
+{
+    p->in_region = al(n ? n : 1, 256);
+    p->out_region = p->ws_region = 0;
+    switch (kernel) {
+    case CRYSTAL_K_NOP:
+        p->d2h = n;
+        break;
+    case CRYSTAL_K_MD5:
+        p->out_region = 256;
+        p->d2h = 16;
+        break;
+    case CRYSTAL_K_MD5_DIRECT: {
+        uint32_t seg = 4096;
+        if (params) {
+            const auto *dp = static_cast<const crystal_direct_params *>(params);
+            if (dp->segment_bytes)
+                seg = dp->segment_bytes;
+        }
+        if (seg % 64 || seg > (1u << 30)) {
+            *why = "segment_bytes must be a multiple of 64 and <= 2^30";
+            return false;
+        }
+        if (j)
+            j->seg_bytes = seg;
+        const uint64_t nseg = (n + seg - 1) / seg;
+        p->d2h = 16 * (nseg + 1);
+        p->out_region = al(p->d2h, 256);
+        break;
+    }
+    case CRYSTAL_K_CDC: {
+        CdcParams cp;
+        if (!cdc_resolve(static_cast<const crystal_cdc_params *>(params), &cp, why))
+            return false;
+        CdcGeom g = cdc_geometry(n, cp);
+        const uint64_t cap = cdc_max_chunks(n, cp);
+        p->d2h = 8 + 24 * cap;
+        p->out_region = al(p->d2h, 256);
+        p->ws_region = al(g.total, 256);
+        if (j) {
+            j->cp = cp;
+            j->g = g;
+            j->cap = cap;
+        }
+        break;
+    }
+    default:
+        *why = "unknown kernel id";
+        return false;
+    }
+    return true;
+}
+
+struct Lib {
+    crystal_config cfg;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_dispatch, cv_done, cv_pool;
+    std::vector<std::unique_ptr<std::condition_variable>> cv_stream;
+    std::deque<Job *> outstanding;
+    std::vector<std::deque<Job *>> running;
+    RangeAlloc dev_alloc, host_alloc;
+    uint8_t *dev_slab = nullptr, *host_slab = nullptr;
+    bool own_dev = false;
+    std::vector<hipStream_t> streams;
+    bool own_streams = false;
+    std::vector<hipEvent_t> events;
+    std::vector<hipEvent_t> free_events;
+    std::set<crystal_buf *> bufs;
+    std::thread dispatcher;
+    std::vector<std::thread> completers;
+    bool stop_dispatch = false, stop_complete = false;
+    uint32_t inflight = 0;
+    uint32_t rr = 0;
+    uint64_t submitted = 0, completed = 0, failed = 0, bytes_in = 0, bytes_out = 0;
+};
+
+static std::mutex g_init_mu;
+static Lib *g_lib = nullptr;
+
+// The done flag lives in task->internal[1]; status is written before the
+// callback runs, done after it returns, so a finished task may be freed.
+static inline int *done_flag(const crystal_task *t)
+{
+    return reinterpret_cast<int *>(const_cast<void **>(&t->internal[1]));
+}
+
+static void finish_task(Lib *L, crystal_task *t, int status)
+{
+    t->t_done_ns = now_ns();
+    t->status = status;
+    if (t->callback)
+        t->callback(t, t->user);
+    {
+        std::lock_guard<std::mutex> lk(L->mu);
+        __atomic_store_n(done_flag(t), 1, __ATOMIC_RELEASE);
+    }
+    L->cv_done.notify_all();
+}
+
+static int pick_stream(Lib *L)
+{
+    const int S = (int)L->streams.size();
+    int best = -1;
+    size_t best_n = 0;
+    for (int k = 0; k < S; k++) {
+        const int s = (int)((L->rr + k) % S);
+        const size_t q = L->running[s].size();
+        if (best < 0 || q < best_n) {
+            best = s;
+            best_n = q;
+        }
+    }
+    L->rr = (L->rr + 1) % S;
+    return best;
+}
+
+// Enqueue copy-in, kernels, copy-out and the completion event.
+static hipError_t enqueue(Lib *L, Job *j)
+{
+    hipStream_t st = L->streams[j->stream];
+    uint8_t *base = L->dev_slab + j->dev_off;
+    uint8_t *d_in = base;
+    uint8_t *d_out = base + j->in_region;
+    hipError_t e = hipSuccess;
+    if (j->n) {
+        e = hipMemcpyAsync(d_in, j->in->host, j->n, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess)
+            return e;
+    }
+    switch (j->kernel) {
+    case CRYSTAL_K_NOP:
+        e = launch_nop(st);
+        d_out = d_in;
+        break;
+    case CRYSTAL_K_MD5:
+        e = launch_md5_whole(d_in, j->n, d_out, st);
+        break;
+    case CRYSTAL_K_MD5_DIRECT: {
+        JobTable jt{nullptr, nullptr, nullptr, 0, j->n};
+        const uint64_t nseg = (j->n + j->seg_bytes - 1) / j->seg_bytes;
+        e = launch_md5_segments(d_in, jt, j->seg_bytes, nseg, d_out, st);
+        if (e == hipSuccess)
+            e = launch_md5_roots(d_out, jt, j->seg_bytes, d_out + 16 * nseg, st);
+        break;
+    }
+    case CRYSTAL_K_CDC: {
+        uint8_t *d_ws = d_out + al(j->d2h, 256);
+        uint64_t *cnt = reinterpret_cast<uint64_t *>(d_out);
+        uint64_t *ends = cnt + 1;
+        e = launch_cdc_candidates(d_in, j->g, j->cp, d_ws, st);
+        if (e == hipSuccess)
+            e = launch_cdc_select(j->g, j->cp, d_ws, cnt, ends, j->cap, st);
+        if (e == hipSuccess)
+            e = launch_md5_chunks(d_in, ends, cnt, j->cap, nullptr, st);
+        break;
+    }
+    }
+    if (e != hipSuccess)
+        return e;
+    if (j->d2h) {
+        e = hipMemcpyAsync(j->out->host, d_out, j->d2h, hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipEventRecord(j->ev, st);
+}
+
+static void release_job_resources(Lib *L, Job *j)
+{
+    // caller holds L->mu
+    L->dev_alloc.release(j->dev_off, j->need);
+    L->free_events.push_back(j->ev);
+    L->inflight--;
+    j->in->refs--;
+    j->out->refs--;
+}
+
+static void dispatcher_main(Lib *L)
+{
+    hipSetDevice(L->device);
+    std::unique_lock<std::mutex> lk(L->mu);
+    for (;;) {
+        if (L->stop_dispatch)
+            break;
+        if (L->outstanding.empty()) {
+            L->cv_dispatch.wait(lk);
+            continue;
+        }
+        Job *j = L->outstanding.front();
+        size_t off = 0;
+        if (L->inflight >= L->cfg.max_in_flight || L->free_events.empty() ||
+            !L->dev_alloc.alloc(j->need, &off)) {
+            L->cv_dispatch.wait(lk); // a completion frees room
+            continue;
+        }
+        L->outstanding.pop_front();
+        L->inflight++;
+        j->dev_off = off;
+        j->ev = L->free_events.back();
+        L->free_events.pop_back();
+        j->stream = pick_stream(L);
+        j->t->stream_index = j->stream;
+        lk.unlock();
+        j->t->t_admit_ns = now_ns();
+        hipError_t e = enqueue(L, j);
+        if (e != hipSuccess) {
+            // drain whatever was enqueued before releasing the region
+            hipStreamSynchronize(L->streams[j->stream]);
+            set_error(CRYSTAL_EDEVICE, "job enqueue: %s", hipGetErrorString(e));
+            lk.lock();
+            release_job_resources(L, j);
+            L->failed++;
+            lk.unlock();
+            finish_task(L, j->t, CRYSTAL_EDEVICE);
+            delete j;
+            lk.lock();
+            continue;
+        }
+        lk.lock();
+        L->running[j->stream].push_back(j);
+        L->cv_stream[j->stream]->notify_one();
+    }
+}
+
+static void completer_main(Lib *L, int s)
+{
+    hipSetDevice(L->device);
+    std::unique_lock<std::mutex> lk(L->mu);
+    for (;;) {
+        if (L->running[s].empty()) {
+            if (L->stop_complete)
+                break;
+            L->cv_stream[s]->wait(lk);
+            continue;
+        }
+        Job *j = L->running[s].front();
+        lk.unlock();
+        hipError_t e = hipEventSynchronize(j->ev);
+        int status = CRYSTAL_OK;
+        size_t out_bytes = j->d2h;
+        if (e != hipSuccess) {
+            status = CRYSTAL_EDEVICE;
+            set_error(CRYSTAL_EDEVICE, "job execution: %s", hipGetErrorString(e));
+        } else if (j->kernel == CRYSTAL_K_CDC) {
+            uint64_t nc;
+            memcpy(&nc, j->out->host, 8);
+            if (nc > j->cap)
+                status = CRYSTAL_EDEVICE;
+            else
+                out_bytes = 8 + 24 * nc;
+        }
+        j->t->out_bytes = status == CRYSTAL_OK ? out_bytes : 0;
+        lk.lock();
+        L->running[s].pop_front();
+        release_job_resources(L, j);
+        if (status == CRYSTAL_OK) {
+            L->completed++;
+            L->bytes_in += j->n;
+            L->bytes_out += out_bytes;
+        } else {
+            L->failed++;
+        }
+        lk.unlock();
+        L->cv_dispatch.notify_one();
+        finish_task(L, j->t, status);
+        delete j;
+        lk.lock();
+    }
+}
+
+static Lib *lib_or_fail()
+{
+    Lib *L = g_lib;
+    if (!L)
+        fail(CRYSTAL_ESTATE, "library not initialised (crystal_init)");
+    return L;
+}
+
+} // namespace crystal
+
+using namespace crystal;
+
+extern "C" {
+
+size_t crystal_output_bytes(int kernel_id, size_t in_bytes, const void *params)
+{
+    JobPlan p;
+    const char *why = "";
+    if (!plan_job(kernel_id, in_bytes, params, nullptr, &p, &why))
+        return 0;
+    return p.d2h;
+}
+
+int crystal_init(const crystal_config *cfg_in)
+{
+    std::lock_guard<std::mutex> g(g_init_mu);
+    if (g_lib)
+        return fail(CRYSTAL_ESTATE, "already initialised");
+    if (!cfg_in || cfg_in->max_input_bytes == 0)
+        return fail(CRYSTAL_EINVAL, "max_input_bytes must be > 0");
+    crystal_config cfg = *cfg_in;
+    if (cfg.n_streams == 0)
+        cfg.n_streams = 4;
+    if (cfg.n_streams > 64)
+        return fail(CRYSTAL_EINVAL, "n_streams must be <= 64");
+    if (cfg.max_in_flight == 0)
+        cfg.max_in_flight = 4 * cfg.n_streams;
+    // largest output and device need over all kernels for the largest input
+    size_t max_out = 0, max_need = 0;
+    for (int k = 0; k <= CRYSTAL_K_MD5; k++) {
+        JobPlan p;
+        const char *why;
+        if (plan_job(k, cfg.max_input_bytes, nullptr, nullptr, &p, &why)) {
+            max_out = std::max(max_out, p.d2h);
+            max_need = std::max(max_need, p.in_region + p.out_region + p.ws_region);
+        }
+    }
+    if (cfg.max_output_bytes == 0)
+        cfg.max_output_bytes = max_out;
+    if (cfg.host_pool_bytes == 0)
+        cfg.host_pool_bytes = 4 * (cfg.max_input_bytes + cfg.max_output_bytes);
+    if (cfg.device_pool_bytes == 0)
+        cfg.device_pool_bytes = std::max<size_t>(8 * max_need, 256ull << 20);
+    cfg.host_pool_bytes = al(cfg.host_pool_bytes, 4096);
+    cfg.device_pool_bytes &= ~(size_t)255;
+
+    std::unique_ptr<Lib> L(new Lib);
+    L->cfg = cfg;
+    L->device = cfg.device;
+    hipError_t e = hipSetDevice(cfg.device);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipSetDevice");
+    if (cfg.device_slab) {
+        L->dev_slab = static_cast<uint8_t *>(cfg.device_slab);
+    } else {
+        e = hipMalloc((void **)&L->dev_slab, cfg.device_pool_bytes);
+        if (e != hipSuccess)
+            return fail(CRYSTAL_ENOMEM, "device slab of %zu bytes: %s", cfg.device_pool_bytes,
+                        hipGetErrorString(e));
+        L->own_dev = true;
+    }
+    e = hipHostMalloc((void **)&L->host_slab, cfg.host_pool_bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        if (L->own_dev)
+            hipFree(L->dev_slab);
+        return fail(CRYSTAL_ENOMEM, "pinned host slab of %zu bytes: %s", cfg.host_pool_bytes,
+                    hipGetErrorString(e));
+    }
+    L->dev_alloc.reset(cfg.device_pool_bytes);
+    L->host_alloc.reset(cfg.host_pool_bytes);
+    L->streams.resize(cfg.n_streams);
+    if (cfg.streams) {
+        for (uint32_t s = 0; s < cfg.n_streams; s++)
+            L->streams[s] = static_cast<hipStream_t>(cfg.streams[s]);
+    } else {
+        L->own_streams = true;
+        for (uint32_t s = 0; s < cfg.n_streams; s++) {
+            e = hipStreamCreateWithFlags(&L->streams[s], hipStreamNonBlocking);
+            if (e != hipSuccess)
+                return hip_fail(e, "hipStreamCreate");
+        }
+    }
+    const uint32_t n_ev = cfg.max_in_flight + 1;
+    for (uint32_t i = 0; i < n_ev; i++) {
+        hipEvent_t ev;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipEventCreate");
+        L->events.push_back(ev);
+        L->free_events.push_back(ev);
+    }
+    L->running.resize(cfg.n_streams);
+    for (uint32_t s = 0; s < cfg.n_streams; s++)
+        L->cv_stream.emplace_back(new std::condition_variable);
+    Lib *raw = L.release();
+    raw->dispatcher = std::thread(dispatcher_main, raw);
+    for (uint32_t s = 0; s < cfg.n_streams; s++)
+        raw->completers.emplace_back(completer_main, raw, (int)s);
+    g_lib = raw;
+    return CRYSTAL_OK;
+}
+
+int crystal_finalize(void)
+{
+    std::lock_guard<std::mutex> g(g_init_mu);
+    Lib *L = g_lib;
+    if (!L)
+        return fail(CRYSTAL_ESTATE, "not initialised");
+    std::deque<Job *> cancelled;
+    {
+        std::lock_guard<std::mutex> lk(L->mu);
+        L->stop_dispatch = true;
+        cancelled.swap(L->outstanding);
+    }
+    L->cv_dispatch.notify_all();
+    L->dispatcher.join();
+    for (Job *j : cancelled) {
+        {
+            std::lock_guard<std::mutex> lk(L->mu);
+            j->in->refs--;
+            j->out->refs--;
+            L->failed++;
+        }
+        finish_task(L, j->t, CRYSTAL_ECANCELED);
+        delete j;
+    }
+    {
+        std::lock_guard<std::mutex> lk(L->mu);
+        L->stop_complete = true;
+    }
+    for (auto &cv : L->cv_stream)
+        cv->notify_all();
+    for (auto &th : L->completers)
+        th.join();
+    hipSetDevice(L->device);
+    for (hipEvent_t ev : L->events)
+        hipEventDestroy(ev);
+    if (L->own_streams)
+        for (hipStream_t s : L->streams)
+            hipStreamDestroy(s);
+    if (L->own_dev)
+        hipFree(L->dev_slab);
+    hipHostFree(L->host_slab);
+    for (crystal_buf *b : L->bufs)
+        delete b;
+    g_lib = nullptr;
+    delete L;
+    return CRYSTAL_OK;
+}
+
+int crystal_buffer_acquire(size_t bytes, int flags, crystal_buf **out)
+{
+    Lib *L = lib_or_fail();
+    if (!L)
+        return CRYSTAL_ESTATE;
+    if (!out)
+        return fail(CRYSTAL_EINVAL, "out is NULL");
+    const size_t len = al(bytes ? bytes : 1, 4096);
+    if (len > L->host_alloc.size())
+        return fail(CRYSTAL_EINVAL, "%zu bytes exceed the host pool (%zu)", bytes,
+                    L->host_alloc.size());
+    std::unique_lock<std::mutex> lk(L->mu);
+    size_t off;
+    while (!L->host_alloc.alloc(len, &off)) {
+        if (flags & CRYSTAL_NONBLOCK)
+            return fail(CRYSTAL_EAGAIN, "host pool exhausted");
+        if (L->stop_dispatch)
+            return fail(CRYSTAL_ESTATE, "finalizing");
+        L->cv_pool.wait(lk);
+    }
+    crystal_buf *b = new crystal_buf;
+    b->host = L->host_slab + off;
+    b->size = bytes;
+    b->pool_off = off;
+    b->pool_len = len;
+    b->pooled = true;
+    b->refs = 0;
+    L->bufs.insert(b);
+    *out = b;
+    return CRYSTAL_OK;
+}
+
+int crystal_buffer_wrap(void *host_ptr, size_t bytes, crystal_buf **out)
+{
+    Lib *L = lib_or_fail();
+    if (!L)
+        return CRYSTAL_ESTATE;
+    if (!out || (!host_ptr && bytes))
+        return fail(CRYSTAL_EINVAL, "null pointer argument");
+    crystal_buf *b = new crystal_buf;
+    b->host = host_ptr;
+    b->size = bytes;
+    b->pool_off = b->pool_len = 0;
+    b->pooled = false;
+    b->refs = 0;
+    std::lock_guard<std::mutex> lk(L->mu);
+    L->bufs.insert(b);
+    *out = b;
+    return CRYSTAL_OK;
+}
+
+int crystal_buffer_release(crystal_buf *b)
+{
+    Lib *L = lib_or_fail();
+    if (!L)
+        return CRYSTAL_ESTATE;
+    if (!b)
+        return fail(CRYSTAL_EINVAL, "buffer is NULL");
+    {
+        std::lock_guard<std::mutex> lk(L->mu);
+        if (!L->bufs.count(b))
+            return fail(CRYSTAL_EINVAL, "unknown buffer");
+        if (b->refs.load() > 0)
+            return fail(CRYSTAL_EBUSY, "buffer in use by an unfinished task");
+        if (b->pooled)
+            L->host_alloc.release(b->pool_off, b->pool_len);
+        L->bufs.erase(b);
+    }
+    const bool pooled = b->pooled;
+    delete b;
+    if (pooled)
+        L->cv_pool.notify_all();
+    return CRYSTAL_OK;
+}
+
+void *crystal_buffer_host(crystal_buf *b) { return b ? b->host : nullptr; }
+size_t crystal_buffer_size(const crystal_buf *b) { return b ? b->size : 0; }
+
+int crystal_submit(crystal_task *t, int kernel_id, crystal_buf *in, crystal_buf *out)
+{
+    Lib *L = lib_or_fail();
+    if (!L)
+        return CRYSTAL_ESTATE;
+    if (!t || !in || !out)
+        return fail(CRYSTAL_EINVAL, "task, in and out are required");
+    const size_t n = t->in_bytes;
+    if (n > in->size)
+        return fail(CRYSTAL_EINVAL, "in_bytes %zu > input buffer %zu", n, in->size);
+    if (n > L->cfg.max_input_bytes)
+        return fail(CRYSTAL_EINVAL, "in_bytes %zu > max_input_bytes %zu", n,
+                    L->cfg.max_input_bytes);
+    Job *j = new Job();
+    JobPlan p;
+    const char *why = "";
+    if (!plan_job(kernel_id, n, t->params, j, &p, &why)) {
+        delete j;
+        return fail(CRYSTAL_EINVAL, "%s", why);
+    }
+    if (out->size < p.d2h) {
+        delete j;
+        return fail(CRYSTAL_EINVAL, "output buffer %zu < required %zu", out->size, p.d2h);
+    }
+    j->t = t;
+    j->kernel = kernel_id;
+    j->in = in;
+    j->out = out;
+    j->n = n;
+    j->in_region = p.in_region;
+    j->need = p.in_region + p.out_region + p.ws_region;
+    j->d2h = p.d2h;
+    if (j->need > L->dev_alloc.size()) {
+        delete j;
+        return fail(CRYSTAL_EINVAL, "job needs %zu device bytes > pool %zu", j->need,
+                    L->dev_alloc.size());
+    }
+    t->status = CRYSTAL_PENDING;
+    t->out_bytes = 0;
+    t->stream_index = -1;
+    t->t_admit_ns = t->t_done_ns = 0;
+    __atomic_store_n(done_flag(t), 0, __ATOMIC_RELEASE);
+    t->internal[0] = j;
+    t->t_submit_ns = now_ns();
+    {
+        std::lock_guard<std::mutex> lk(L->mu);
+        if (L->stop_dispatch) {
+            delete j;
+            return fail(CRYSTAL_ESTATE, "finalizing");
+        }
+        in->refs++;
+        out->refs++;
+        L->outstanding.push_back(j);
+        L->submitted++;
+    }
+    L->cv_dispatch.notify_one();
+    return CRYSTAL_OK;
+}
+
+int crystal_poll(const crystal_task *t)
+{
+    if (!t)
+        return fail(CRYSTAL_EINVAL, "task is NULL");
+    if (!__atomic_load_n(done_flag(t), __ATOMIC_ACQUIRE))
+        return 0;
+    return t->status == CRYSTAL_OK ? 1 : t->status;
+}
+
+int crystal_wait(crystal_task *t, int64_t timeout_ns)
+{
+    Lib *L = lib_or_fail();
+    if (!L)
+        return CRYSTAL_ESTATE;
+    if (!t)
+        return fail(CRYSTAL_EINVAL, "task is NULL");
+    std::unique_lock<std::mutex> lk(L->mu);
+    auto done = [&] { return __atomic_load_n(done_flag(t), __ATOMIC_ACQUIRE) != 0; };
+    if (timeout_ns < 0) {
+        L->cv_done.wait(lk, done);
+    } else if (!L->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), done)) {
+        return fail(CRYSTAL_ETIMEDOUT, "task not finished within %lld ns",
+                    (long long)timeout_ns);
+    }
+    return t->status;
+}
+
+int crystal_get_stats(crystal_stats *s)
+{
+    Lib *L = lib_or_fail();
+    if (!L)
+        return CRYSTAL_ESTATE;
+    if (!s)
+        return fail(CRYSTAL_EINVAL, "stats is NULL");
+    std::lock_guard<std::mutex> lk(L->mu);
+    s->submitted = L->submitted;
+    s->completed = L->completed;
+    s->failed = L->failed;
+    s->bytes_in = L->bytes_in;
+    s->bytes_out = L->bytes_out;
+    s->device_pool_bytes = L->dev_alloc.size();
+    s->device_pool_free = L->dev_alloc.free_bytes();
+    s->device_pool_min_free = L->dev_alloc.min_free();
+    s->host_pool_bytes = L->host_alloc.size();
+    s->host_pool_free = L->host_alloc.free_bytes();
+    s->outstanding = (uint32_t)L->outstanding.size();
+    uint32_t r = 0;
+    for (auto &q : L->running)
+        r += (uint32_t)q.size();
+    s->running = r;
+    return CRYSTAL_OK;
+}
+
+} // extern "C"
