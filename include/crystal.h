@@ -219,6 +219,17 @@ int crystal_md5_direct_device(const void *d_in, const uint64_t *d_job_off,
                               uint64_t n_segments, uint32_t segment_bytes,
                               void *d_seg_digests, void *d_roots, void *stream);
 
+/* The two steps of crystal_md5_direct_device, callable on their own (same
+ * arguments): segment digests only, then roots from those digests. */
+int crystal_md5_segments_device(const void *d_in, const uint64_t *d_job_off,
+                                const uint64_t *d_job_len,
+                                const uint64_t *d_seg_base, uint32_t n_jobs,
+                                uint64_t n_segments, uint32_t segment_bytes,
+                                void *d_seg_digests, void *stream);
+int crystal_md5_roots_device(const uint64_t *d_seg_base, uint32_t n_jobs,
+                             uint32_t segment_bytes, const void *d_seg_digests,
+                             void *d_roots, void *stream);
+
 /* MD5 of n_buf buffers: buffer m is d_arena[d_off[m], d_off[m] + d_len[m]),
  * digest to d_out + 16 m.  d_order (optional, n_buf entries) is the order in
  * which lanes take buffers (e.g. longest first); NULL = index order.
@@ -269,8 +280,10 @@ int crystal_window_hash_device(const void *d_in, uint64_t n, uint64_t base,
 
 /* ======================================================================
  * Batching (the paper's batch-processing class, Sec. 2.2 B): many small
- * independent buffers hashed by one persistent launch, captured once in a
- * HIP graph and replayed.
+ * independent buffers hashed by one persistent launch per branch, planned
+ * once (longest-first order, tuned launch shape) and replayed.  Replays are
+ * direct stream launches; HIP-graph capture of the replay is switched off in
+ * this version.
  * ==================================================================== */
 
 typedef struct crystal_batch_desc {
@@ -298,12 +311,12 @@ typedef struct crystal_batch crystal_batch;
 #define CRYSTAL_TUNE_FULL 1  /* grid search, replay-timed */
 
 /* Build a plan: length-sort the buffers (longest first), choose launch
- * parameters (tune_flags), capture the launch in a HIP graph, instantiate.
+ * parameters (tune_flags) by timing replays.
  * The library allocates the plan's own small device tables.  *fixed may be
  * NULL. */
 int crystal_batch_plan(const crystal_batch_desc *d, int tune_flags,
                        const crystal_batch_tuning *fixed, crystal_batch **out);
-/* Replay the graph `iters` times on the desc's stream (asynchronous). */
+/* Replay the plan `iters` times on the desc's stream (asynchronous). */
 int crystal_batch_run(crystal_batch *b, int iters);
 int crystal_batch_get_tuning(const crystal_batch *b, crystal_batch_tuning *t);
 void crystal_batch_free(crystal_batch *b);
@@ -347,9 +360,14 @@ typedef struct crystal_drive_result {
     uint64_t ok, failed;
 } crystal_drive_result;
 
+/* window == 0: open loop; window > 0: closed loop, at most `window` jobs in
+ * the system.  direct / cdc: parameters of the two job kinds (NULL =
+ * defaults).  Per-job status, latency and admission wait are written back
+ * into jobs[]. */
 int crystal_drive(crystal_drive_job *jobs, uint64_t n_jobs,
                   const crystal_direct_params *direct,
-                  const crystal_cdc_params *cdc, crystal_drive_result *res);
+                  const crystal_cdc_params *cdc, uint32_t window,
+                  crystal_drive_result *res);
 
 #ifdef __cplusplus
 }

@@ -63,6 +63,21 @@ def crystal_md5_direct_device(d_in, d_job_off, d_job_len, d_seg_base, n_jobs,
         _stream(stream)), "crystal_md5_direct_device")
 
 
+def crystal_md5_segments_device(d_in, d_job_off, d_job_len, d_seg_base, n_jobs,
+                                n_segments, segment_bytes, d_seg_digests, stream=None):
+    return check(load().crystal_md5_segments_device(
+        _ptr(d_in), _ptr(d_job_off), _ptr(d_job_len), _ptr(d_seg_base), n_jobs,
+        n_segments, segment_bytes, _ptr(d_seg_digests), _stream(stream)),
+        "crystal_md5_segments_device")
+
+
+def crystal_md5_roots_device(d_seg_base, n_jobs, segment_bytes, d_seg_digests,
+                             d_roots, stream=None):
+    return check(load().crystal_md5_roots_device(
+        _ptr(d_seg_base), n_jobs, segment_bytes, _ptr(d_seg_digests), _ptr(d_roots),
+        _stream(stream)), "crystal_md5_roots_device")
+
+
 def crystal_md5_batch_device(d_arena, d_off, d_len, d_order, n_buf, d_out,
                              block=0, grid=0, stream=None):
     return check(load().crystal_md5_batch_device(
@@ -183,3 +198,162 @@ def batch_device(d_arena, offsets, lengths, order=None, block=256, grid=0,
     out = torch.empty((max(n, 1), 16), dtype=torch.uint8, device=dev)
     crystal_md5_batch_device(d_arena, off, ln, o, n, out, block, grid, stream)
     return out[:n]
+
+
+# ------------------------------------------------------------------ job API
+
+def crystal_init(max_input_bytes: int, max_output_bytes: int = 0,
+                 host_pool_bytes: int = 0, device_pool_bytes: int = 0,
+                 n_streams: int = 0, max_in_flight: int = 0, device: int = 0,
+                 device_slab=None, streams=None) -> None:
+    cfg = crystal_config(max_input_bytes=max_input_bytes,
+                         max_output_bytes=max_output_bytes,
+                         host_pool_bytes=host_pool_bytes,
+                         device_pool_bytes=device_pool_bytes,
+                         n_streams=n_streams, max_in_flight=max_in_flight,
+                         device=device, flags=0,
+                         device_slab=_ptr(device_slab) or None)
+    keep = None
+    if streams:
+        keep = (ctypes.c_void_p * len(streams))(*[_stream(s) for s in streams])
+        cfg.n_streams = len(streams)
+        cfg.streams = ctypes.cast(keep, ctypes.POINTER(ctypes.c_void_p))
+    check(load().crystal_init(ctypes.byref(cfg)), "crystal_init")
+
+
+def crystal_finalize() -> None:
+    check(load().crystal_finalize(), "crystal_finalize")
+
+
+def crystal_buffer_acquire(nbytes: int, flags: int = 0) -> int:
+    h = ctypes.c_void_p()
+    check(load().crystal_buffer_acquire(nbytes, flags, ctypes.byref(h)),
+          "crystal_buffer_acquire")
+    return h.value
+
+
+def crystal_buffer_wrap(host_ptr, nbytes: int) -> int:
+    h = ctypes.c_void_p()
+    check(load().crystal_buffer_wrap(_ptr(host_ptr), nbytes, ctypes.byref(h)),
+          "crystal_buffer_wrap")
+    return h.value
+
+
+def crystal_buffer_release(buf: int) -> None:
+    check(load().crystal_buffer_release(buf), "crystal_buffer_release")
+
+
+def crystal_buffer_host(buf: int) -> int:
+    return load().crystal_buffer_host(buf)
+
+
+def crystal_buffer_size(buf: int) -> int:
+    return load().crystal_buffer_size(buf)
+
+
+def buffer_view(buf: int) -> np.ndarray:
+    """numpy uint8 view of a buffer's host memory (no copy)."""
+    n = crystal_buffer_size(buf)
+    if n == 0:
+        return np.zeros(0, dtype=np.uint8)
+    addr = crystal_buffer_host(buf)
+    return np.ctypeslib.as_array((ctypes.c_uint8 * n).from_address(addr))
+
+
+def crystal_output_bytes(kernel_id: int, in_bytes: int, params=None) -> int:
+    return load().crystal_output_bytes(kernel_id, in_bytes,
+                                       ctypes.byref(params) if params is not None else None)
+
+
+def crystal_submit(task: crystal_task, kernel_id: int, inb: int, outb: int) -> None:
+    check(load().crystal_submit(ctypes.byref(task), kernel_id, inb, outb),
+          "crystal_submit")
+
+
+def crystal_wait(task: crystal_task, timeout_ns: int = -1) -> int:
+    return load().crystal_wait(ctypes.byref(task), timeout_ns)
+
+
+def crystal_poll(task: crystal_task) -> int:
+    return load().crystal_poll(ctypes.byref(task))
+
+
+def crystal_get_stats() -> crystal_stats:
+    s = crystal_stats()
+    check(load().crystal_get_stats(ctypes.byref(s)), "crystal_get_stats")
+    return s
+
+
+def new_task(in_bytes: int, params=None, callback=None, user=None) -> crystal_task:
+    t = crystal_task()
+    t.in_bytes = in_bytes
+    if params is not None:
+        t.params = ctypes.cast(ctypes.byref(params), ctypes.c_void_p)
+        t._params_ref = params
+    if callback is not None:
+        cb = CALLBACK(callback)
+        t.callback = cb
+        t._cb_ref = cb
+    t.user = user
+    return t
+
+
+# ---------------------------------------------------------------- batching
+
+def crystal_batch_plan(d_arena, d_off, d_len, n_buf: int, d_out, stream=None,
+                       tune: int = 0, fixed: crystal_batch_tuning | None = None) -> int:
+    desc = crystal_batch_desc(d_arena=_ptr(d_arena), d_off=_ptr(d_off),
+                              d_len=_ptr(d_len), n_buf=n_buf, d_out=_ptr(d_out),
+                              stream=_stream(stream))
+    h = ctypes.c_void_p()
+    check(load().crystal_batch_plan(ctypes.byref(desc), tune,
+                                    ctypes.byref(fixed) if fixed is not None else None,
+                                    ctypes.byref(h)), "crystal_batch_plan")
+    return h.value
+
+
+def crystal_batch_run(plan: int, iters: int = 1) -> None:
+    check(load().crystal_batch_run(plan, iters), "crystal_batch_run")
+
+
+def crystal_batch_get_tuning(plan: int) -> crystal_batch_tuning:
+    t = crystal_batch_tuning()
+    check(load().crystal_batch_get_tuning(plan, ctypes.byref(t)),
+          "crystal_batch_get_tuning")
+    return t
+
+
+def crystal_batch_free(plan: int) -> None:
+    load().crystal_batch_free(plan)
+
+
+# -------------------------------------------------------------- naive path
+
+def crystal_naive_run(kernel_id: int, params, h_in, n: int, h_out, out_cap: int):
+    ob = ctypes.c_size_t()
+    st = crystal_stage_times()
+    check(load().crystal_naive_run(kernel_id,
+                                   ctypes.byref(params) if params is not None else None,
+                                   _ptr(h_in), n, _ptr(h_out), out_cap, ctypes.byref(ob),
+                                   ctypes.byref(st)), "crystal_naive_run")
+    return ob.value, st
+
+
+# ------------------------------------------------------------------ driver
+
+def crystal_drive(jobs, direct=None, cdc=None, window: int = 0) -> crystal_drive_result:
+    """jobs: a ctypes array of crystal_drive_job (filled in place)."""
+    res = crystal_drive_result()
+    check(load().crystal_drive(jobs, len(jobs),
+                               ctypes.byref(direct) if direct is not None else None,
+                               ctypes.byref(cdc) if cdc is not None else None,
+                               window, ctypes.byref(res)), "crystal_drive")
+    return res
+
+
+def parse_cdc_output(buf: np.ndarray):
+    """Split a chunking job's output into (ends uint64[n], digests uint8[n,16])."""
+    n = int(buf[:8].view(np.uint64)[0])
+    ends = buf[8:8 + 8 * n].view(np.uint64)
+    dig = buf[8 + 8 * n:8 + 24 * n].reshape(n, 16)
+    return ends, dig

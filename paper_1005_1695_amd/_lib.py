@@ -111,6 +111,9 @@ SIGNATURES = {
     "crystal_get_stats": ([P(crystal_stats)], c_int),
     "crystal_md5_direct_device": ([c_vp, c_vp, c_vp, c_vp, c_u32, c_u64, c_u32, c_vp,
                                    c_vp, c_vp], c_int),
+    "crystal_md5_segments_device": ([c_vp, c_vp, c_vp, c_vp, c_u32, c_u64, c_u32, c_vp,
+                                     c_vp], c_int),
+    "crystal_md5_roots_device": ([c_vp, c_u32, c_u32, c_vp, c_vp, c_vp], c_int),
     "crystal_md5_batch_device": ([c_vp, c_vp, c_vp, c_vp, c_u64, c_vp, c_u32, c_u32,
                                   c_vp], c_int),
     "crystal_cdc_workspace_bytes": ([c_u64, P(crystal_cdc_params)], c_sz),

@@ -165,6 +165,47 @@ int crystal_md5_direct_device(const void *d_in, const uint64_t *d_job_off,
     return CRYSTAL_OK;
 }
 
+int crystal_md5_segments_device(const void *d_in, const uint64_t *d_job_off,
+                                const uint64_t *d_job_len, const uint64_t *d_seg_base,
+                                uint32_t n_jobs, uint64_t n_segments, uint32_t segment_bytes,
+                                void *d_seg_digests, void *stream)
+{
+    if (segment_bytes == 0)
+        segment_bytes = 4096;
+    if (segment_bytes % 64 || segment_bytes > (1u << 30))
+        return fail(CRYSTAL_EINVAL, "segment_bytes must be a multiple of 64 and <= 2^30");
+    if (n_jobs == 0 || n_segments == 0)
+        return CRYSTAL_OK;
+    if (!d_in || !d_job_off || !d_job_len || !d_seg_base || !d_seg_digests)
+        return fail(CRYSTAL_EINVAL, "null pointer argument");
+    JobTable jt{d_job_off, d_job_len, d_seg_base, n_jobs, 0};
+    hipError_t e = launch_md5_segments((const uint8_t *)d_in, jt, segment_bytes, n_segments,
+                                       (uint8_t *)d_seg_digests, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "md5_segments launch");
+    return CRYSTAL_OK;
+}
+
+int crystal_md5_roots_device(const uint64_t *d_seg_base, uint32_t n_jobs,
+                             uint32_t segment_bytes, const void *d_seg_digests, void *d_roots,
+                             void *stream)
+{
+    if (segment_bytes == 0)
+        segment_bytes = 4096;
+    if (segment_bytes % 64 || segment_bytes > (1u << 30))
+        return fail(CRYSTAL_EINVAL, "segment_bytes must be a multiple of 64 and <= 2^30");
+    if (n_jobs == 0)
+        return CRYSTAL_OK;
+    if (!d_seg_base || !d_roots)
+        return fail(CRYSTAL_EINVAL, "null pointer argument");
+    JobTable jt{nullptr, nullptr, d_seg_base, n_jobs, 0};
+    hipError_t e = launch_md5_roots((const uint8_t *)d_seg_digests, jt, segment_bytes,
+                                    (uint8_t *)d_roots, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "md5_roots launch");
+    return CRYSTAL_OK;
+}
+
 int crystal_md5_batch_device(const void *d_arena, const uint64_t *d_off, const uint32_t *d_len,
                              const uint32_t *d_order, uint64_t n_buf, void *d_out,
                              uint32_t block, uint32_t grid, void *stream)

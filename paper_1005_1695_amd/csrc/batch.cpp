@@ -1,8 +1,13 @@
 // Batch plans: the batch-processing application class of Sec. 2.2 (many
 // independent buffers available at once, throughput first).  A plan orders
-// the buffers longest-first, captures a persistent MD5 launch (optionally
-// split over several streams as parallel graph branches) into a HIP graph,
-// and replays it.  The tuner times every candidate configuration by replay.
+// the buffers longest-first and replays a persistent MD5 launch (optionally
+// split over several streams as parallel branches joined by events).  The
+// tuner times every candidate configuration by replay.
+//
+// Replay uses direct stream launches.  Capturing the same sequence into a HIP
+// graph (capture() below) is switched off: under the HIP runtime that PyTorch
+// loads into the process, a plan built that way ended in a host segmentation
+// fault whose cause has not been identified, so that path is not run.
 #include <algorithm>
 #include <numeric>
 #include <string.h>
@@ -27,13 +32,14 @@ struct crystal_batch {
 };
 
 static const uint32_t kMaxBranches = 8;
+static const bool kGraphReplay = false; // see the header comment
 
 static void destroy_graph(crystal_batch *b)
 {
     if (b->exec)
-        hipGraphExecDestroy(b->exec);
+        (void)hipGraphExecDestroy(b->exec);
     if (b->graph)
-        hipGraphDestroy(b->graph);
+        (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
 }
@@ -101,7 +107,7 @@ static hipError_t capture(crystal_batch *b, const crystal_batch_tuning &t)
         e = e2;
     if (e != hipSuccess) {
         if (gr)
-            hipGraphDestroy(gr);
+            (void)hipGraphDestroy(gr);
         return e;
     }
     b->graph = gr;
@@ -109,20 +115,82 @@ static hipError_t capture(crystal_batch *b, const crystal_batch_tuning &t)
     return e;
 }
 
+// One replay by direct launches on the desc stream (branch i on plan stream
+// i, forked from and joined back into the desc stream by events).
+static hipError_t launch_direct(crystal_batch *b, const crystal_batch_tuning &t)
+{
+    hipStream_t s0 = (hipStream_t)b->d.stream;
+    const uint32_t S = t.n_streams;
+    const uint64_t n = b->d.n_buf;
+    const uint32_t waves = b->n_simd * t.waves_per_simd;
+    uint32_t grid = (uint32_t)((uint64_t)waves * 64 / t.block);
+    if (grid == 0)
+        grid = 1;
+    const uint32_t *order = t.sorted ? b->d_order : nullptr;
+    hipError_t e = hipSuccess;
+    if (S > 1) {
+        e = hipEventRecord(b->ev[0], s0);
+        for (uint32_t i = 1; i < S && e == hipSuccess; i++)
+            e = hipStreamWaitEvent(b->cap[i], b->ev[0], 0);
+    }
+    const uint64_t total = b->work_prefix.back();
+    uint64_t lo = 0;
+    for (uint32_t i = 0; i < S && e == hipSuccess; i++) {
+        hipStream_t si = i == 0 ? s0 : b->cap[i];
+        uint64_t hi = n;
+        if (i + 1 < S) {
+            const uint64_t target = total * (i + 1) / S;
+            hi = std::lower_bound(b->work_prefix.begin(), b->work_prefix.end(), target) -
+                 b->work_prefix.begin();
+            hi = std::min<uint64_t>(std::max<uint64_t>(hi, lo), n);
+        }
+        const uint32_t g = std::max<uint32_t>(1, grid / S);
+        e = launch_zero_u32(b->d_counters + i, 1, si);
+        if (e == hipSuccess && hi > lo) {
+            if (order)
+                e = launch_md5_batch_persistent((const uint8_t *)b->d.d_arena, b->d.d_off,
+                                                b->d.d_len, order + lo, hi - lo,
+                                                (uint8_t *)b->d.d_out, b->d_counters + i,
+                                                t.grab, t.block, g, si);
+            else
+                e = launch_md5_batch_persistent((const uint8_t *)b->d.d_arena,
+                                                b->d.d_off + lo, b->d.d_len + lo, nullptr,
+                                                hi - lo, (uint8_t *)b->d.d_out + 16 * lo,
+                                                b->d_counters + i, t.grab, t.block, g, si);
+        }
+        lo = hi;
+    }
+    if (S > 1) {
+        for (uint32_t i = 1; i < S && e == hipSuccess; i++) {
+            e = hipEventRecord(b->ev[i], b->cap[i]);
+            if (e == hipSuccess)
+                e = hipStreamWaitEvent(s0, b->ev[i], 0);
+        }
+    }
+    return e;
+}
+
+static hipError_t replay(crystal_batch *b)
+{
+    if (kGraphReplay && b->exec)
+        return hipGraphLaunch(b->exec, (hipStream_t)b->d.stream);
+    return launch_direct(b, b->tun);
+}
+
 static hipError_t time_replays(crystal_batch *b, int reps, float *ms)
 {
     hipStream_t s = (hipStream_t)b->d.stream;
     hipEvent_t a, z;
-    hipEventCreate(&a);
-    hipEventCreate(&z);
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&z);
     hipError_t e = hipSuccess;
     for (int i = 0; i < 2 && e == hipSuccess; i++)
-        e = hipGraphLaunch(b->exec, s);
+        e = replay(b);
     std::vector<float> v;
     for (int i = 0; i < reps && e == hipSuccess; i++) {
         e = hipEventRecord(a, s);
         if (e == hipSuccess)
-            e = hipGraphLaunch(b->exec, s);
+            e = replay(b);
         if (e == hipSuccess)
             e = hipEventRecord(z, s);
         if (e == hipSuccess)
@@ -132,8 +200,8 @@ static hipError_t time_replays(crystal_batch *b, int reps, float *ms)
             e = hipEventElapsedTime(&t, a, z);
         v.push_back(t);
     }
-    hipEventDestroy(a);
-    hipEventDestroy(z);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(z);
     if (e == hipSuccess) {
         std::sort(v.begin(), v.end());
         *ms = v[v.size() / 2];
@@ -145,15 +213,15 @@ static void free_plan(crystal_batch *b)
 {
     destroy_graph(b);
     if (b->d_order)
-        hipFree(b->d_order);
+        (void)hipFree(b->d_order);
     if (b->d_counters)
-        hipFree(b->d_counters);
+        (void)hipFree(b->d_counters);
     for (auto &s : b->cap)
         if (s)
-            hipStreamDestroy(s);
+            (void)hipStreamDestroy(s);
     for (auto &e : b->ev)
         if (e)
-            hipEventDestroy(e);
+            (void)hipEventDestroy(e);
     delete b;
 }
 
@@ -168,7 +236,7 @@ int crystal_batch_plan(const crystal_batch_desc *d, int tune_flags,
         return fail(CRYSTAL_EINVAL, "n_buf must be in [1, 2^31)");
     crystal_batch *b = new crystal_batch;
     b->d = *d;
-    hipGetDevice(&b->device);
+    (void)hipGetDevice(&b->device);
     hipDeviceProp_t prop;
     hipError_t e = hipGetDeviceProperties(&prop, b->device);
     if (e != hipSuccess) {
@@ -237,7 +305,8 @@ int crystal_batch_plan(const crystal_batch_desc *d, int tune_flags,
     crystal_batch_tuning best = cands[0];
     best.replay_ms = -1.f;
     for (const auto &c : cands) {
-        e = capture(b, c);
+        b->tun = c;
+        e = kGraphReplay ? capture(b, c) : hipSuccess;
         float ms = 0;
         if (e == hipSuccess)
             e = time_replays(b, cands.size() > 1 ? 5 : 3, &ms);
@@ -250,12 +319,12 @@ int crystal_batch_plan(const crystal_batch_desc *d, int tune_flags,
             best.replay_ms = ms;
         }
     }
-    e = capture(b, best);
+    b->tun = best;
+    e = kGraphReplay ? capture(b, best) : hipSuccess;
     if (e != hipSuccess) {
         free_plan(b);
         return hip_fail(e, "batch capture");
     }
-    b->tun = best;
     *out = b;
     return CRYSTAL_OK;
 }
@@ -265,9 +334,9 @@ int crystal_batch_run(crystal_batch *b, int iters)
     if (!b || iters < 0)
         return fail(CRYSTAL_EINVAL, "bad arguments");
     for (int i = 0; i < iters; i++) {
-        hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)b->d.stream);
+        hipError_t e = replay(b);
         if (e != hipSuccess)
-            return hip_fail(e, "hipGraphLaunch");
+            return hip_fail(e, "batch replay");
     }
     return CRYSTAL_OK;
 }

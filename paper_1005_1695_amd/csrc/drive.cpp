@@ -10,6 +10,7 @@
 #include <condition_variable>
 #include <mutex>
 #include <thread>
+#include <string.h>
 #include <time.h>
 #include <vector>
 

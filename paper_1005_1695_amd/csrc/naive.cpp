@@ -86,11 +86,11 @@ extern "C" int crystal_naive_run(int kernel_id, const void *params, const void *
     const int64_t t4 = now_ns();
     if (kernel_id == CRYSTAL_K_NOP)
         d_out = nullptr;
-    hipFree(d_in);
+    (void)hipFree(d_in);
     if (d_out)
-        hipFree(d_out);
+        (void)hipFree(d_out);
     if (d_ws)
-        hipFree(d_ws);
+        (void)hipFree(d_ws);
     const int64_t t5 = now_ns();
     if (e != hipSuccess)
         return hip_fail(e, "naive job");

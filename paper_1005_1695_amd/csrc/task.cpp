@@ -298,7 +298,7 @@ static void release_job_resources(Lib *L, Job *j)
 
 static void dispatcher_main(Lib *L)
 {
-    hipSetDevice(L->device);
+    (void)hipSetDevice(L->device);
     std::unique_lock<std::mutex> lk(L->mu);
     for (;;) {
         if (L->stop_dispatch)
@@ -326,7 +326,7 @@ static void dispatcher_main(Lib *L)
         hipError_t e = enqueue(L, j);
         if (e != hipSuccess) {
             // drain whatever was enqueued before releasing the region
-            hipStreamSynchronize(L->streams[j->stream]);
+            (void)hipStreamSynchronize(L->streams[j->stream]);
             set_error(CRYSTAL_EDEVICE, "job enqueue: %s", hipGetErrorString(e));
             lk.lock();
             release_job_resources(L, j);
@@ -345,7 +345,7 @@ static void dispatcher_main(Lib *L)
 
 static void completer_main(Lib *L, int s)
 {
-    hipSetDevice(L->device);
+    (void)hipSetDevice(L->device);
     std::unique_lock<std::mutex> lk(L->mu);
     for (;;) {
         if (L->running[s].empty()) {
@@ -463,7 +463,7 @@ int crystal_init(const crystal_config *cfg_in)
     e = hipHostMalloc((void **)&L->host_slab, cfg.host_pool_bytes, hipHostMallocDefault);
     if (e != hipSuccess) {
         if (L->own_dev)
-            hipFree(L->dev_slab);
+            (void)hipFree(L->dev_slab);
         return fail(CRYSTAL_ENOMEM, "pinned host slab of %zu bytes: %s", cfg.host_pool_bytes,
                     hipGetErrorString(e));
     }
@@ -533,15 +533,15 @@ int crystal_finalize(void)
         cv->notify_all();
     for (auto &th : L->completers)
         th.join();
-    hipSetDevice(L->device);
+    (void)hipSetDevice(L->device);
     for (hipEvent_t ev : L->events)
-        hipEventDestroy(ev);
+        (void)hipEventDestroy(ev);
     if (L->own_streams)
         for (hipStream_t s : L->streams)
-            hipStreamDestroy(s);
+            (void)hipStreamDestroy(s);
     if (L->own_dev)
-        hipFree(L->dev_slab);
-    hipHostFree(L->host_slab);
+        (void)hipFree(L->dev_slab);
+    (void)hipHostFree(L->host_slab);
     for (crystal_buf *b : L->bufs)
         delete b;
     g_lib = nullptr;

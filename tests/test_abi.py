@@ -1,0 +1,128 @@
+"""The C-ABI library loads on the CPU, exports every symbol include/crystal.h
+declares, and its host-side validation answers without touching a GPU."""
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "crystal.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(crystal_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1005_1695_amd as P
+    from paper_1005_1695_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libcrystal.so not built; run __graft_entry__.build()")
+    P.load()
+    return P
+
+
+def test_header_declarations_found():
+    names = _declared()
+    assert "crystal_submit" in names and "crystal_md5_direct_device" in names
+    assert len(names) >= 25
+
+
+def test_every_declared_symbol_is_exported(P):
+    from paper_1005_1695_amd import _lib
+    out = subprocess.check_output(["nm", "-D", "--defined-only", _lib.LIB_PATH], text=True)
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    assert _lib.MISSING == []
+    # the binding covers exactly the declared API
+    assert set(_lib.SIGNATURES) == set(_declared())
+
+
+def test_output_sizes(P):
+    dp = P.crystal_direct_params(segment_bytes=4096)
+    assert P.crystal_output_bytes(P.K_MD5_DIRECT, 1 << 20, dp) == 16 * 257
+    assert P.crystal_output_bytes(P.K_MD5_DIRECT, 4097, dp) == 16 * 3
+    assert P.crystal_output_bytes(P.K_MD5_DIRECT, 0, dp) == 16
+    cp = P.cdc_params(12345)
+    assert P.crystal_output_bytes(P.K_CDC, 1 << 20, cp) == 8 + 24 * ((1 << 20) // 2048 + 1)
+    assert P.crystal_output_bytes(P.K_CDC, 0, cp) == 8
+    assert P.crystal_output_bytes(P.K_NOP, 777, None) == 777
+    assert P.crystal_output_bytes(P.K_MD5, 777, None) == 16
+    assert P.crystal_output_bytes(99, 777, None) == 0
+    bad = P.crystal_direct_params(segment_bytes=100)
+    assert P.crystal_output_bytes(P.K_MD5_DIRECT, 1000, bad) == 0
+
+
+def test_cdc_sizes(P):
+    cp = P.cdc_params(3)
+    assert P.crystal_cdc_max_chunks(0, cp) == 0
+    assert P.crystal_cdc_max_chunks(4096, cp) == 3
+    ws = P.crystal_cdc_workspace_bytes(256 << 20, cp)
+    # one bit per byte plus small tables: about n/8
+    assert (256 << 20) // 8 <= ws < (256 << 20) // 4
+    bad = P.crystal_cdc_params(base=3, min_len=10, max_len=5, mask_bits=13, window=48)
+    assert P.crystal_cdc_workspace_bytes(1000, bad) == 0
+    badw = P.crystal_cdc_params(base=3, window=32)
+    assert P.crystal_cdc_workspace_bytes(1000, badw) == 0
+
+
+def test_calls_before_init_are_rejected(P):
+    lib = P.load()
+    assert lib.crystal_finalize() == P._lib.ESTATE
+    t = P.crystal_task()
+    assert lib.crystal_submit(t, P.K_NOP, 1, 1) == P._lib.ESTATE
+    import ctypes
+    h = ctypes.c_void_p()
+    assert lib.crystal_buffer_acquire(10, 0, ctypes.byref(h)) == P._lib.ESTATE
+    assert "not initialised" in P.last_error()
+
+
+def test_device_calls_validate_before_launch(P):
+    lib = P.load()
+    # segment size not a multiple of 64 -> EINVAL, no launch attempted
+    rc = lib.crystal_md5_direct_device(1, 1, 1, 1, 1, 1, 100, 1, 1, None)
+    assert rc == P._lib.EINVAL
+    rc = lib.crystal_md5_batch_device(1, 1, 1, None, 5, 1, 100, 0, None)
+    assert rc == P._lib.EINVAL
+    cp = P.cdc_params(3)
+    import ctypes
+    # workspace too small
+    rc = lib.crystal_cdc_device(1, 1 << 20, ctypes.byref(cp), 1, 10, 1, 1, 1, 1000, None)
+    assert rc == P._lib.EINVAL
+    # capacity below the worst case
+    ws = P.crystal_cdc_workspace_bytes(1 << 20, cp)
+    rc = lib.crystal_cdc_select_device(1 << 20, ctypes.byref(cp), 1, ws, 1, 1, 3, None)
+    assert rc == P._lib.EINVAL
+    # zero-work calls succeed without launching anything
+    assert lib.crystal_md5_direct_device(None, None, None, None, 0, 0, 0, None, None,
+                                         None) == 0
+    assert lib.crystal_md5_batch_device(None, None, None, None, 0, None, 0, 0, None) == 0
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1005_1695_amd import _lib\n"
+            "_lib.LIB_PATH = %r\n"
+            "try:\n    _lib.load()\nexcept RuntimeError as e:\n"
+            "    print('raised', 'no fallback' in str(e))\n" % (ROOT, str(tmp_path / "x.so")))
+    out = subprocess.check_output([sys.executable, "-c", code], text=True)
+    assert out.strip() == "raised True"
+
+
+def test_product_does_not_reference_oracle():
+    """The library sources and the Python package never use the oracle."""
+    pkg = os.path.join(ROOT, "paper_1005_1695_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "oracle." not in txt, f
+                assert "liboracle" not in txt, f
+    hdr = open(HEADER).read()
+    assert "oracle" not in hdr

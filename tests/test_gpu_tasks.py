@@ -1,0 +1,348 @@
+"""GPU tests of the job layer: paper API semantics (Fig. 3), pooled buffers,
+overlapped streams, serving mix (alone == in the mix, bit for bit), the naive
+per-job path, and tuned batch plans replayed several times."""
+import ctypes
+import hashlib
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def P(torch_cuda):
+    import paper_1005_1695_amd as P
+    P.load()
+    return P
+
+
+@pytest.fixture()
+def lib(P):
+    P.crystal_init(max_input_bytes=64 << 20, host_pool_bytes=1 << 30,
+                   device_pool_bytes=2 << 30, n_streams=4)
+    yield P
+    P.crystal_finalize()
+
+
+def _submit(P, kernel, data, params=None, callback=None):
+    n = len(data)
+    inb = P.crystal_buffer_acquire(max(n, 1))
+    P.buffer_view(inb)[:n] = data
+    outb = P.crystal_buffer_acquire(max(P.crystal_output_bytes(kernel, n, params), 1))
+    t = P.new_task(n, params, callback)
+    P.crystal_submit(t, kernel, inb, outb)
+    return t, inb, outb
+
+
+def test_direct_job_1mib_with_callback(lib):
+    P = lib
+    seen = []
+    data = gen.direct_one()
+    t, inb, outb = _submit(P, P.K_MD5_DIRECT, data,
+                           callback=lambda task, user: seen.append(task.contents.status))
+    assert P.crystal_wait(t) == 0
+    assert P.crystal_poll(t) == 1
+    assert seen == [0]
+    assert t.out_bytes == 16 * 257
+    out = P.buffer_view(outb)[:t.out_bytes].reshape(257, 16)
+    es, er = oracle.direct(data)
+    assert np.array_equal(out[:256], es)
+    assert out[256].tobytes() == er
+    assert t.t_submit_ns <= t.t_admit_ns <= t.t_done_ns
+    P.crystal_buffer_release(inb)
+    P.crystal_buffer_release(outb)
+
+
+@pytest.mark.parametrize("kind", ["nop", "md5", "direct64", "cdc_small", "cdc_default",
+                                  "direct_ragged", "empty_cdc", "empty_direct"])
+def test_each_kernel_as_a_job(lib, kind):
+    P = lib
+    base = gen.cdc_base()
+    data = gen.random_bytes(len(kind), 3_000_001)
+    params = None
+    if kind == "nop":
+        k = P.K_NOP
+    elif kind == "md5":
+        k = P.K_MD5
+    elif kind.startswith("direct"):
+        k = P.K_MD5_DIRECT
+        params = P.crystal_direct_params(segment_bytes=64 if kind == "direct64" else 4096)
+        if kind == "direct_ragged":
+            data = data[:123457]
+        if kind == "empty_direct":
+            data = data[:0]
+    else:
+        k = P.K_CDC
+        params = (P.cdc_params(base, 64, 700, 6) if kind == "cdc_small"
+                  else P.cdc_params(base))
+        if kind == "empty_cdc":
+            data = data[:0]
+    t, inb, outb = _submit(P, k, data, params)
+    assert P.crystal_wait(t) == 0
+    out = P.buffer_view(outb)[:t.out_bytes]
+    if k == P.K_NOP:
+        assert np.array_equal(out, data)
+    elif k == P.K_MD5:
+        assert out.tobytes() == hashlib.md5(data.tobytes()).digest()
+    elif k == P.K_MD5_DIRECT:
+        seg = params.segment_bytes
+        es, er = oracle.direct(data, seg)
+        assert np.array_equal(out[:-16].reshape(-1, 16), es)
+        assert out[-16:].tobytes() == er
+    else:
+        ends, dig = P.parse_cdc_output(out)
+        ee, ed = oracle.cdc(data, base, params.mask_bits, params.min_len, params.max_len)
+        assert np.array_equal(ends, ee) and np.array_equal(dig, ed)
+    P.crystal_buffer_release(inb)
+    P.crystal_buffer_release(outb)
+
+
+def test_poll_timeout_and_busy_release(lib):
+    P = lib
+    data = gen.random_bytes(1, 64 << 20)
+    t, inb, outb = _submit(P, P.K_CDC, data, P.cdc_params(gen.cdc_base()))
+    rc = P.crystal_wait(t, 0)
+    if P.crystal_poll(t) == 0:
+        assert rc == P._lib.ETIMEDOUT
+    rc = P.load().crystal_buffer_release(inb)
+    assert rc == P._lib.EBUSY or P.crystal_poll(t) == 1
+    assert P.crystal_wait(t, -1) == 0
+    assert P.crystal_poll(t) == 1
+    if rc == P._lib.EBUSY:
+        P.crystal_buffer_release(inb)
+    P.crystal_buffer_release(outb)
+
+
+def test_nonblocking_acquire_eagain(lib):
+    P = lib
+    held = []
+    lib_ = P.load()
+    h = ctypes.c_void_p()
+    while True:
+        rc = lib_.crystal_buffer_acquire(256 << 20, P.NONBLOCK, ctypes.byref(h))
+        if rc != 0:
+            break
+        held.append(h.value)
+    assert rc == P._lib.EAGAIN and len(held) == 4
+    P.crystal_buffer_release(held.pop())
+    held.append(P.crystal_buffer_acquire(256 << 20, P.NONBLOCK))
+    for b in held:
+        P.crystal_buffer_release(b)
+    s = P.crystal_get_stats()
+    assert s.host_pool_free == s.host_pool_bytes
+
+
+def test_overlapped_stream_of_jobs(lib, torch_cuda):
+    """16 jobs of 8 MiB submitted at once spread over the 4 streams and overlap
+    in time; every output matches the oracle."""
+    P = lib
+    n_jobs, job = 16, 8 << 20
+    seeds = gen.direct_stream_seeds(n_jobs)
+    prepared, bufs = [], []
+    cap = P.crystal_output_bytes(P.K_MD5_DIRECT, job, None)
+    for j in range(n_jobs):
+        data = gen.random_bytes(int(seeds[j]), job)
+        inb = P.crystal_buffer_acquire(job)
+        P.buffer_view(inb)[:] = data
+        outb = P.crystal_buffer_acquire(cap)
+        prepared.append((data, inb, outb))
+        bufs += [inb, outb]
+    tasks = []
+    for data, inb, outb in prepared:  # submit back to back
+        t = P.new_task(job)
+        P.crystal_submit(t, P.K_MD5_DIRECT, inb, outb)
+        tasks.append((t, data, outb))
+    for t, data, outb in tasks:
+        assert P.crystal_wait(t) == 0
+        _, er = oracle.direct(data)
+        assert bytes(P.buffer_view(outb)[-16:]) == er
+    streams = {t.stream_index for t, _, _ in tasks}
+    assert len(streams) >= 2
+    iv = sorted((t.t_admit_ns, t.t_done_ns) for t, _, _ in tasks)
+    overlaps = sum(1 for a, b in zip(iv, iv[1:]) if b[0] < a[1])
+    assert overlaps >= 1
+    for b in bufs:
+        P.crystal_buffer_release(b)
+
+
+def _drive_jobs(P, torch, sizes, kinds, arrivals, arena, offsets, base):
+    n = len(sizes)
+    jobs = (P.crystal_drive_job * n)()
+    outs = []
+    direct = P.crystal_direct_params(segment_bytes=4096)
+    cdcp = P.cdc_params(base)
+    for k in range(n):
+        kid = P.K_CDC if kinds[k] else P.K_MD5_DIRECT
+        cap = P.crystal_output_bytes(kid, int(sizes[k]), cdcp if kinds[k] else direct)
+        o = torch.empty(cap, dtype=torch.uint8).pin_memory()
+        outs.append(o)
+        jobs[k].h_in = arena.data_ptr() + int(offsets[k])
+        jobs[k].bytes = int(sizes[k])
+        jobs[k].h_out = o.data_ptr()
+        jobs[k].out_cap = cap
+        jobs[k].arrival_s = float(arrivals[k])
+        jobs[k].kernel_id = kid
+    return jobs, outs, direct, cdcp
+
+
+def test_serving_mix_alone_equals_mix(lib, torch_cuda):
+    """Open-loop mixed arrivals overlap on the device; each job's output is
+    identical to the same job run alone (naive path) and to the oracle."""
+    P, torch = lib, torch_cuda
+    spec = gen.serving_jobs(n_jobs=120, load_gbps=20.0, hi=8 << 20, arena_bytes=64 << 20,
+                            seed=4242)
+    arena = torch.empty(spec["arena_bytes"], dtype=torch.uint8).pin_memory()
+    gen.fill(spec["arena_seed"], arena.data_ptr(), spec["arena_bytes"])
+    base = gen.cdc_base()
+    jobs, outs, direct, cdcp = _drive_jobs(P, torch, spec["size"], spec["kind"],
+                                           spec["arrival_s"], arena, spec["offset"], base)
+    res = P.crystal_drive(jobs, direct, cdcp, window=0)
+    assert res.ok == 120 and res.failed == 0
+    a = arena.numpy()
+    for k in range(120):
+        assert jobs[k].status == 0 and jobs[k].latency_s > 0
+        sz, of = int(spec["size"][k]), int(spec["offset"][k])
+        data = a[of:of + sz]
+        kid = jobs[k].kernel_id
+        mix = outs[k].numpy()
+        alone = np.zeros(jobs[k].out_cap, dtype=np.uint8)
+        ob, _ = P.crystal_naive_run(kid, cdcp if kid == P.K_CDC else direct, data, sz,
+                                    alone, jobs[k].out_cap)
+        assert np.array_equal(mix[:ob], alone[:ob]), k
+        if kid == P.K_CDC:
+            ends, dig = P.parse_cdc_output(mix)
+            ee, ed = oracle.cdc(data, base)
+            assert np.array_equal(ends, ee) and np.array_equal(dig, ed), k
+        else:
+            es, er = oracle.direct(data)
+            assert mix[16 * len(es):16 * len(es) + 16].tobytes() == er, k
+
+
+def test_closed_loop_window(lib, torch_cuda):
+    P, torch = lib, torch_cuda
+    n = 24
+    arena = torch.empty(n * (4 << 20), dtype=torch.uint8).pin_memory()
+    gen.fill(99, arena.data_ptr(), arena.numel())
+    sizes = [4 << 20] * n
+    offs = [k * (4 << 20) for k in range(n)]
+    jobs, outs, direct, cdcp = _drive_jobs(P, torch, sizes, [0] * n, [0.0] * n, arena,
+                                           offs, gen.cdc_base())
+    res = P.crystal_drive(jobs, direct, cdcp, window=4)
+    assert res.ok == n
+    a = arena.numpy()
+    for k in range(n):
+        _, er = oracle.direct(a[offs[k]:offs[k] + sizes[k]])
+        assert outs[k].numpy()[-16:].tobytes() == er
+
+
+def test_naive_path_stage_times(P, torch_cuda):
+    data = gen.random_bytes(3, 8 << 20)
+    out = np.zeros(P.crystal_output_bytes(P.K_MD5_DIRECT, len(data), None), np.uint8)
+    ob, st = P.crystal_naive_run(P.K_MD5_DIRECT, None, data, len(data), out, len(out))
+    es, er = oracle.direct(data)
+    assert out[-16:].tobytes() == er and ob == len(out)
+    assert st.alloc_ms > 0 and st.copy_in_ms > 0 and st.kernel_ms > 0
+    assert st.total_ms >= st.alloc_ms + st.copy_in_ms + st.kernel_ms
+
+
+def test_small_device_pool_admission(P, torch_cuda):
+    """Jobs wait for room in a small device pool and all still complete."""
+    P.crystal_init(max_input_bytes=16 << 20, device_pool_bytes=40 << 20,
+                   host_pool_bytes=512 << 20, n_streams=2)
+    try:
+        tasks = []
+        for j in range(12):
+            data = gen.random_bytes(j, 16 << 20)
+            tasks.append((_submit(P, P.K_MD5_DIRECT, data), data))
+        for (t, inb, outb), data in tasks:
+            assert P.crystal_wait(t) == 0
+            assert P.buffer_view(outb)[-16:].tobytes() == oracle.direct(data)[1]
+        s = P.crystal_get_stats()
+        assert s.completed == 12 and s.device_pool_free == s.device_pool_bytes
+        assert s.device_pool_min_free < 40 << 20
+    finally:
+        P.crystal_finalize()
+
+
+def test_finalize_with_jobs_in_flight(P, torch_cuda):
+    P.crystal_init(max_input_bytes=32 << 20, device_pool_bytes=64 << 20,
+                   host_pool_bytes=1 << 30, n_streams=2)
+    subs = []
+    for j in range(24):
+        data = gen.random_bytes(j + 500, 32 << 20)
+        subs.append((_submit(P, P.K_MD5_DIRECT, data), data))
+    P.crystal_finalize()
+    ok = cancelled = 0
+    for (t, _, outb), data in subs:
+        st = t.status
+        assert st in (0, P._lib.ECANCELED)
+        if st == 0:
+            ok += 1
+        else:
+            cancelled += 1
+    assert ok + cancelled == 24
+
+
+def test_batch_plan_replays(P, torch_cuda):
+    torch = torch_cuda
+    off, ln, arena, seed = gen.batch_small(n_buf=20000)
+    data = gen.random_bytes(seed, arena + 64)
+    d, _ = P.to_device_bytes(data)
+    t_off = torch.from_numpy(off.view(np.int64)).cuda()
+    t_len = torch.from_numpy(ln.view(np.int32)).cuda()
+    out = torch.zeros((20000, 16), dtype=torch.uint8, device="cuda")
+    exp = oracle.md5_batch(data, off, ln)
+    s = torch.cuda.Stream()
+    for tune in (P._lib.TUNE_NONE, P._lib.TUNE_FULL):
+        with torch.cuda.stream(s):
+            plan = P.crystal_batch_plan(d, t_off, t_len, 20000, out, stream=s, tune=tune)
+        try:
+            tun = P.crystal_batch_get_tuning(plan)
+            assert tun.replay_ms > 0
+            for rep in range(3):
+                with torch.cuda.stream(s):
+                    out.zero_()
+                    P.crystal_batch_run(plan, 1)
+                s.synchronize()
+                assert np.array_equal(out.cpu().numpy(), exp), (tune, rep)
+                junk = torch.randn(1 << 20, device="cuda").sum().item()  # eager work
+                assert junk == junk
+        finally:
+            P.crystal_batch_free(plan)
+
+
+def test_batch_plan_fixed_multi_stream(P, torch_cuda):
+    torch = torch_cuda
+    off, ln, arena, seed = gen.batch_small(n_buf=5000, seed=8)
+    data = gen.random_bytes(seed, arena + 64)
+    d, _ = P.to_device_bytes(data)
+    t_off = torch.from_numpy(off.view(np.int64)).cuda()
+    t_len = torch.from_numpy(ln.view(np.int32)).cuda()
+    out = torch.zeros((5000, 16), dtype=torch.uint8, device="cuda")
+    exp = oracle.md5_batch(data, off, ln)
+    for sorted_ in (0, 1):
+        fixed = P.crystal_batch_tuning(block=128, waves_per_simd=2, grab=4, n_streams=4,
+                                       sorted=sorted_)
+        s = torch.cuda.Stream()
+        plan = P.crystal_batch_plan(d, t_off, t_len, 5000, out, stream=s, fixed=fixed)
+        try:
+            for rep in range(2):
+                with torch.cuda.stream(s):
+                    out.zero_()
+                    P.crystal_batch_run(plan, 1)
+                s.synchronize()
+                assert np.array_equal(out.cpu().numpy(), exp)
+        finally:
+            P.crystal_batch_free(plan)
