@@ -7,10 +7,15 @@ over the job's concatenated segment digests.
 
 * One step = direct hashing of all 256 jobs with their inputs already
   resident in HBM: the segment kernel over all 524 288 segments, then the
-  root kernel over the 256 jobs.  `value` is hashed GB/s (10^9 bytes/s) of
-  that step.  Each kernel is timed with HIP events on the stream it runs on.
+  root kernel over the 256 jobs.  Consecutive steps are pipelined the way
+  the job layer overlaps consecutive jobs: step k's root kernel (256 serial
+  chains on a second stream) runs while step k+1's segment kernel runs, with
+  the segment digests double-buffered.  `value` is hashed GB/s (10^9
+  bytes/s) over the K timed steps, all of whose work completes inside the
+  timed region.  Each kernel is timed with HIP events on its own stream.
 * `e2e` (never `value`): the same 256 jobs fed from pinned host memory
-  through the job layer (pooled device buffers, 4 streams, copy/compute
+  through the job layer (pooled device buffers, a copy-in stream and 2
+  compute streams, copy/compute
   overlap) and through the naive per-job path (hipMalloc, blocking copy,
   same kernels, blocking copy, hipFree), with per-job p50/p99 latency, plus
   the measured pinned host-to-device copy ceiling.
@@ -83,6 +88,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-e2e", action="store_true", help="skip the host-fed legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--e2e-streams", type=int, default=2)
+    ap.add_argument("--e2e-window", type=int, default=12)
     ap.add_argument("--cpu-jobs", type=int, default=0,
                     help="jobs in the CPU oracle sample (0 = sized to ~10 s)")
     args = ap.parse_args()
@@ -118,37 +125,66 @@ def main() -> int:
     t_off = torch.from_numpy(offs.view(np.int64)).to(dev)
     t_len = torch.from_numpy(lens.view(np.int64)).to(dev)
     t_base = torch.from_numpy(base.view(np.int64)).to(dev)
-    seg = torch.empty((n_seg, 16), dtype=torch.uint8, device=dev)
-    roots = torch.empty((N_JOBS, 16), dtype=torch.uint8, device=dev)
+    # digests triple-buffered; roots of consecutive steps alternate between two
+    # streams, so two root launches (each 256 serial chains) can be in flight
+    # while the segment kernel of a later step runs
+    NBUF, NROOT = 3, 2
+    segbufs = [torch.empty((n_seg, 16), dtype=torch.uint8, device=dev) for _ in range(NBUF)]
+    rootbufs = [torch.empty((N_JOBS, 16), dtype=torch.uint8, device=dev)
+                for _ in range(NBUF)]
     torch.cuda.synchronize()
 
-    stream = torch.cuda.current_stream()
-    sptr = stream.cuda_stream
-
-    def step():
-        P.crystal_md5_segments_device(d_in, t_off, t_len, t_base, N_JOBS, n_seg, SEGMENT,
-                                      seg, sptr)
-        P.crystal_md5_roots_device(t_base, N_JOBS, SEGMENT, seg, roots, sptr)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    sA = torch.cuda.current_stream()                              # segment kernels
+    sB = [torch.cuda.Stream(device=dev) for _ in range(NROOT)]    # root kernels
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+
+    def run(nsteps, timed):
+        """nsteps pipelined steps; returns per-step event quadruples."""
+        evs = []
+        root_done = []
+        for k in range(nsteps):
+            buf, rbuf = segbufs[k % NBUF], rootbufs[k % NBUF]
+            rs = sB[k % NROOT]
+            e = [torch.cuda.Event(enable_timing=timed) for _ in range(4)]
+            if k >= NBUF:
+                sA.wait_event(root_done[k - NBUF])  # digest buffer is free again
+            e[0].record(sA)
+            P.crystal_md5_segments_device(d_in, t_off, t_len, t_base, N_JOBS, n_seg,
+                                          SEGMENT, buf, sA.cuda_stream)
+            e[1].record(sA)
+            rs.wait_event(e[1])
+            e[2].record(rs)
+            P.crystal_md5_roots_device(t_base, N_JOBS, SEGMENT, buf, rbuf, rs.cuda_stream)
+            e[3].record(rs)
+            root_done.append(e[3])
+            evs.append(e)
+        return evs
+
+    run(args.warmup, False)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(K):
-        ev[k][0].record(stream)
-        P.crystal_md5_segments_device(d_in, t_off, t_len, t_base, N_JOBS, n_seg, SEGMENT,
-                                      seg, sptr)
-        ev[k][1].record(stream)
-        P.crystal_md5_roots_device(t_base, N_JOBS, SEGMENT, seg, roots, sptr)
-        ev[k][2].record(stream)
+    ev = run(K, True)
+    for rs in sB:
+        sA.wait_stream(rs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / K
     seg_ms = statistics.mean(e[0].elapsed_time(e[1]) for e in ev)
-    root_ms = statistics.mean(e[1].elapsed_time(e[2]) for e in ev)
+    root_ms = statistics.mean(e[2].elapsed_time(e[3]) for e in ev)
     value = total / 1e9 / (ms_per_step / 1e3)
+    roots = rootbufs[(K - 1) % NBUF]
+
+    # reference: the same step run back to back without overlap
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(5):
+        P.crystal_md5_segments_device(d_in, t_off, t_len, t_base, N_JOBS, n_seg, SEGMENT,
+                                      segbufs[0], sA.cuda_stream)
+        P.crystal_md5_roots_device(t_base, N_JOBS, SEGMENT, segbufs[0], rootbufs[0],
+                                   sA.cuda_stream)
+    torch.cuda.synchronize()
+    serial_step_ms = (time.perf_counter() - ta) * 1e3 / 5
+    stream = sA
 
     comp = n_seg * compressions(SEGMENT)  # every segment is a full 4 KiB
     seg_ops = comp * OPS_PER_COMPRESSION
@@ -176,7 +212,9 @@ def main() -> int:
                "root_chain_compressions": compressions(16 * (n_seg // N_JOBS)),
                "root_us_per_compression": round(root_ms * 1e3 /
                                                 compressions(16 * (n_seg // N_JOBS)), 4),
-               "root_compressions_total": root_comp}
+               "root_compressions_total": root_comp,
+               "serial_step_ms": round(serial_step_ms, 4),
+               "pipelined_step_ms": round(ms_per_step, 4)}
 
     # ------------------------------------------------- host-fed (PCIe) legs
     e2e = None
@@ -195,9 +233,10 @@ def main() -> int:
             best = ms if best is None else min(best, ms)
         e2e["copy_ceiling_gbps"] = round(cc / 1e9 / (best / 1e3), 2)
 
-        window = 8
+        window = args.e2e_window
         P.crystal_init(max_input_bytes=JOB_BYTES, host_pool_bytes=64 << 20,
-                       device_pool_bytes=1 << 30, n_streams=4, max_in_flight=16)
+                       device_pool_bytes=1 << 30, n_streams=args.e2e_streams,
+                       max_in_flight=max(16, 2 * window))
         try:
             direct = P.crystal_direct_params(segment_bytes=SEGMENT)
             cap = P.crystal_output_bytes(P.K_MD5_DIRECT, JOB_BYTES, direct)
@@ -221,6 +260,7 @@ def main() -> int:
             e2e["pipelined_p99_ms"] = round(pct(best_run[1], 99), 3)
             e2e["pipelined_ok"] = int(best_run[2])
             e2e["pipelined_window"] = window
+            e2e["pipelined_streams"] = args.e2e_streams
             ok_roots = all(bytes(outs[j, cap - 16:].numpy()) == bytes(roots[j].cpu().numpy())
                            for j in (0, 77, 255))
             e2e["pipelined_matches_device_step"] = bool(ok_roots)

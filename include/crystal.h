@@ -102,14 +102,17 @@ typedef struct crystal_config {
     size_t device_pool_bytes; /* device slab from which each admitted job
                                  takes input, output and scratch; 0 = 8 *
                                  per-job need of the largest job */
-    uint32_t n_streams;       /* HIP streams jobs are spread over; 0 = 4 */
-    uint32_t max_in_flight;   /* dispatched but unfinished jobs; 0 = 4*streams */
+    uint32_t n_streams;       /* compute streams jobs are spread over (each
+                                 also carries its jobs' copy-out); one more
+                                 stream carries every copy-in; 0 = 3 */
+    uint32_t max_in_flight;   /* dispatched but unfinished jobs; 0 = 4*n_streams */
     int32_t device;           /* HIP device ordinal */
     uint32_t flags;           /* CRYSTAL_F_* */
     void *device_slab;        /* optional caller-owned device memory of
                                  device_pool_bytes (e.g. from PyTorch); the
                                  library then allocates no device pool itself */
-    void **streams;           /* optional n_streams caller-owned streams */
+    void **streams;           /* optional caller-owned streams: n_streams + 1
+                                 entries, [0] = copy-in, [1..] = compute */
 } crystal_config;
 
 typedef struct crystal_buf crystal_buf; /* opaque pooled/wrapped host buffer */

@@ -214,9 +214,9 @@ def crystal_init(max_input_bytes: int, max_output_bytes: int = 0,
                          device=device, flags=0,
                          device_slab=_ptr(device_slab) or None)
     keep = None
-    if streams:
+    if streams:  # [copy-in stream, compute streams...]
         keep = (ctypes.c_void_p * len(streams))(*[_stream(s) for s in streams])
-        cfg.n_streams = len(streams)
+        cfg.n_streams = len(streams) - 1
         cfg.streams = ctypes.cast(keep, ctypes.POINTER(ctypes.c_void_p))
     check(load().crystal_init(ctypes.byref(cfg)), "crystal_init")
 

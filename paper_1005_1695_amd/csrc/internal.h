@@ -12,12 +12,17 @@ namespace crystal {
 // ------------------------------------------------------------- direct hashing
 // Job table of a multi-job direct-hashing launch.  n_jobs == 0 selects the
 // single-job form: one job at offset 0 of length single_len.
+// out_off == nullptr: segment digests form one array indexed by global
+// segment number and roots go to a separate array.  Otherwise job j's
+// output is its own region at byte offset out_off[j] from the digest base:
+// its segment digests, then its root (the job layer's output layout).
 struct JobTable {
     const uint64_t *off;
     const uint64_t *len;
     const uint64_t *seg_base;
     uint32_t n_jobs;
     uint64_t single_len;
+    const uint64_t *out_off = nullptr;
 };
 
 hipError_t launch_md5_segments(const uint8_t *in, const JobTable &jt,

@@ -6,18 +6,15 @@
 
 namespace crystal {
 
-// Lane s hashes segment s of the launch.  Multi-job launches locate the job
-// by binary search in the segment prefix table (largest j with
-// seg_base[j] <= s), which also skips empty jobs.
-__global__ __launch_bounds__(256) void k_md5_segments(const uint8_t *__restrict__ in,
-                                                      JobTable jt, uint32_t seg_bytes,
-                                                      uint64_t n_segments,
-                                                      uint8_t *__restrict__ dig)
+// Segment s of a launch: locate its job (multi-job launches search the
+// segment prefix table for the largest j with seg_base[j] <= s, which also
+// skips empty jobs), hash it, store its digest at index s.
+__device__ __forceinline__ void md5_one_segment(const uint8_t *__restrict__ in,
+                                                const JobTable &jt, uint32_t seg_bytes,
+                                                uint64_t s, uint8_t *__restrict__ dig)
 {
-    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_segments)
-        return;
     uint64_t off = 0, len = jt.single_len, local = s;
+    uint8_t *dst = dig + 16 * s;
     if (jt.n_jobs) {
         uint32_t lo = 0, hi = jt.n_jobs;
         while (hi - lo > 1) {
@@ -30,6 +27,8 @@ __global__ __launch_bounds__(256) void k_md5_segments(const uint8_t *__restrict_
         off = jt.off[lo];
         len = jt.len[lo];
         local = s - jt.seg_base[lo];
+        if (jt.out_off)
+            dst = dig + jt.out_off[lo] + 16 * local;
     }
     const uint64_t start = local * seg_bytes;
     const uint64_t rem = len - start;
@@ -37,14 +36,32 @@ __global__ __launch_bounds__(256) void k_md5_segments(const uint8_t *__restrict_
     const uint8_t *p = in + off + start;
     uint32_t st[4];
     if (((uintptr_t)p & 15) == 0)
-        md5_message_a16(p, n, st);
+        md5_message_a16_pf(p, n, st);
     else
         md5_message_any(p, n, st);
-    md5_store(dig + 16 * s, st);
+    md5_store(dst, st);
+}
+
+// Grid-stride over segments: the host sizes the grid so every SIMD holds the
+// same number of waves and every lane the same number of segments, so no
+// partial last round of waves is left running on an otherwise idle chip.
+__global__ __launch_bounds__(256) void k_md5_segments(const uint8_t *__restrict__ in,
+                                                      JobTable jt, uint32_t seg_bytes,
+                                                      uint64_t n_segments,
+                                                      uint8_t *__restrict__ dig)
+{
+    const uint64_t G = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n_segments;
+         s += G)
+        md5_one_segment(in, jt, seg_bytes, s, dig);
 }
 
 // Lane j computes the root of job j: MD5 over its segment digests, which are
-// contiguous and 16-byte aligned in the digest array.
+// contiguous and 16-byte aligned in the digest array.  Each lane is one long
+// serial chain with few waves around it, so its loader keeps three 128-byte
+// groups in flight.  (Raising these waves' issue priority was measured to
+// slow a concurrently running segment kernel by far more than it sped the
+// chains up, so they run at the default priority.)
 __global__ __launch_bounds__(64) void k_md5_roots(const uint8_t *__restrict__ dig,
                                                   JobTable jt, uint32_t seg_bytes,
                                                   uint8_t *__restrict__ roots)
@@ -60,9 +77,15 @@ __global__ __launch_bounds__(64) void k_md5_roots(const uint8_t *__restrict__ di
     } else {
         nseg = (jt.single_len + seg_bytes - 1) / seg_bytes;
     }
+    const uint8_t *src = dig + 16 * b0;
+    uint8_t *dst = roots + 16 * j;
+    if (jt.n_jobs && jt.out_off) {
+        src = dig + jt.out_off[j];
+        dst = const_cast<uint8_t *>(src) + 16 * nseg;
+    }
     uint32_t st[4];
-    md5_message_a16(dig + 16 * b0, 16 * nseg, st);
-    md5_store(roots + 16 * j, st);
+    md5_message_a16_ring<3>(src, 16 * nseg, st);
+    md5_store(dst, st);
 }
 
 __global__ __launch_bounds__(64) void k_md5_whole(const uint8_t *__restrict__ in,
@@ -181,14 +204,47 @@ static inline uint32_t blocks_for(uint64_t n, uint32_t b)
     return (uint32_t)((n + b - 1) / b);
 }
 
+// Number of SIMDs of the current device (4 per compute unit), cached.
+static uint32_t device_simds()
+{
+    static int cached_dev = -1;
+    static uint32_t cached = 0;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev != cached_dev || cached == 0) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess ||
+            cu <= 0)
+            cu = 256;
+        cached = 4u * (uint32_t)cu;
+        cached_dev = dev;
+    }
+    return cached;
+}
+
+// Waves per SIMD the segment grid aims for before lanes take more than one
+// segment.  The kernel is bound by the HBM rate of 524 288 independent
+// 4 KiB streams, where more waves in flight measured faster than fewer
+// waves with more segments each; 8 covers the 256 x 8 MiB workload with
+// one segment per lane.
+static const uint32_t kSegWavesPerSimd = 8;
+
 hipError_t launch_md5_segments(const uint8_t *in, const JobTable &jt,
                                uint32_t seg_bytes, uint64_t n_segments,
                                uint8_t *seg_digests, hipStream_t s)
 {
     if (n_segments == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_md5_segments, dim3(blocks_for(n_segments, 256)), dim3(256),
-                       0, s, in, jt, seg_bytes, n_segments, seg_digests);
+    const uint64_t lanes_full = (uint64_t)device_simds() * kSegWavesPerSimd * 64;
+    uint64_t lanes = n_segments;
+    if (n_segments > lanes_full) {
+        // equal segments per lane, then just enough lanes for them
+        const uint64_t per_lane = (n_segments + lanes_full - 1) / lanes_full;
+        lanes = (n_segments + per_lane - 1) / per_lane;
+    }
+    hipLaunchKernelGGL(k_md5_segments, dim3(blocks_for(lanes, 256)), dim3(256), 0, s, in,
+                       jt, seg_bytes, n_segments, seg_digests);
     return hipGetLastError();
 }
 

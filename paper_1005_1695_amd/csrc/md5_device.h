@@ -199,6 +199,111 @@ __device__ __forceinline__ void md5_message_a16(const uint8_t *__restrict__ p,
     md5_finish(st, w, rb, len);
 }
 
+// Same digest as md5_message_a16, software-pipelined: the next 128 bytes are
+// requested before the current 128 bytes are compressed, so a lane keeps one
+// load group in flight behind its own compute.  Used where few waves share a
+// SIMD (long single chains, grids sized to the chip).
+__device__ __forceinline__ void md5_message_a16_pf(const uint8_t *__restrict__ p,
+                                                   uint64_t len, uint32_t st[4])
+{
+    md5_init(st);
+    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+    const uint64_t nb = len >> 6;
+    const uint64_t npairs = nb >> 1;
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    uint4 c0 = z, c1 = z, c2 = z, c3 = z, c4 = z, c5 = z, c6 = z, c7 = z;
+    if (npairs) {
+        c0 = q[0]; c1 = q[1]; c2 = q[2]; c3 = q[3];
+        c4 = q[4]; c5 = q[5]; c6 = q[6]; c7 = q[7];
+    }
+    for (uint64_t k = 0; k < npairs; ++k) {
+        uint4 n0 = z, n1 = z, n2 = z, n3 = z, n4 = z, n5 = z, n6 = z, n7 = z;
+        if (k + 1 < npairs) {
+            const uint4 *r = q + 8 * (k + 1);
+            n0 = r[0]; n1 = r[1]; n2 = r[2]; n3 = r[3];
+            n4 = r[4]; n5 = r[5]; n6 = r[6]; n7 = r[7];
+        }
+        uint32_t x[16];
+        md5_unpack4(x, c0, c1, c2, c3);
+        md5_compress(st, x);
+        md5_unpack4(x, c4, c5, c6, c7);
+        md5_compress(st, x);
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        c4 = n4; c5 = n5; c6 = n6; c7 = n7;
+    }
+    if (nb & 1) {
+        const uint4 *r = q + 8 * npairs;
+        uint4 v0 = r[0], v1 = r[1], v2 = r[2], v3 = r[3];
+        uint32_t x[16];
+        md5_unpack4(x, v0, v1, v2, v3);
+        md5_compress(st, x);
+    }
+    const uint32_t rb = (uint32_t)(len & 63);
+    const uint4 *t = q + 4 * nb;
+    uint4 t0 = rb > 0 ? t[0] : z;
+    uint4 t1 = rb > 16 ? t[1] : z;
+    uint4 t2 = rb > 32 ? t[2] : z;
+    uint4 t3 = rb > 48 ? t[3] : z;
+    uint32_t w[16];
+    md5_unpack4(w, t0, t1, t2, t3);
+    md5_finish(st, w, rb, len);
+}
+
+// Same digest, with D groups of 128 bytes in flight per lane (a ring of D
+// register slots refilled as each is consumed).  For long chains that run
+// with few waves per SIMD, where one group of look-ahead does not cover the
+// load latency.
+template <int D>
+__device__ __forceinline__ void md5_message_a16_ring(const uint8_t *__restrict__ p,
+                                                     uint64_t len, uint32_t st[4])
+{
+    md5_init(st);
+    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+    const uint64_t nb = len >> 6;
+    const uint64_t ng = nb >> 1; // whole 128-byte groups
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    uint4 r[D][8];
+#pragma unroll
+    for (int j = 0; j < D; j++)
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            r[j][k] = (uint64_t)j < ng ? q[8 * j + k] : z;
+    for (uint64_t g = 0; g < ng; g += D) {
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            if (g + j < ng) {
+                uint32_t x[16];
+                md5_unpack4(x, r[j][0], r[j][1], r[j][2], r[j][3]);
+                md5_compress(st, x);
+                md5_unpack4(x, r[j][4], r[j][5], r[j][6], r[j][7]);
+                md5_compress(st, x);
+                if (g + j + D < ng) {
+                    const uint4 *n = q + 8 * (g + j + D);
+#pragma unroll
+                    for (int k = 0; k < 8; k++)
+                        r[j][k] = n[k];
+                }
+            }
+        }
+    }
+    if (nb & 1) {
+        const uint4 *rr = q + 8 * ng;
+        uint4 v0 = rr[0], v1 = rr[1], v2 = rr[2], v3 = rr[3];
+        uint32_t x[16];
+        md5_unpack4(x, v0, v1, v2, v3);
+        md5_compress(st, x);
+    }
+    const uint32_t rb = (uint32_t)(len & 63);
+    const uint4 *t = q + 4 * nb;
+    uint4 t0 = rb > 0 ? t[0] : z;
+    uint4 t1 = rb > 16 ? t[1] : z;
+    uint4 t2 = rb > 32 ? t[2] : z;
+    uint4 t3 = rb > 48 ? t[3] : z;
+    uint32_t w[16];
+    md5_unpack4(w, t0, t1, t2, t3);
+    md5_finish(st, w, rb, len);
+}
+
 // MD5 of a message at any byte address.  Each block is read as 17 aligned
 // dwords starting at the dword that holds its first byte (four 16-byte
 // vectors with 4-byte alignment plus one dword) and realigned with

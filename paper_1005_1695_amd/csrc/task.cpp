@@ -6,13 +6,16 @@
 //   - one dispatcher thread pops the outstanding queue in FIFO order and
 //     admits the head job only when the device slab has room for its input,
 //     output and scratch (first fit) and fewer than max_in_flight jobs are
-//     running; it then enqueues copy-in, kernels, copy-out and an event on
-//     the least-loaded of the library's streams, so consecutive jobs overlap
-//     copy and compute (the three-stage pipeline of Fig. 4);
-//   - one completion thread per stream waits for that stream's jobs in order
-//     (a stream completes in order), returns their device memory, runs the
-//     callback and wakes waiters -- the asynchronous notification the paper
-//     adds on top of a runtime that only offers polling (Sec. 4.1).
+//     running.  The stages of the three-stage pipeline (Fig. 4) go on
+//     separate streams: every copy-in is enqueued on one copy-in stream, so
+//     the host link is never idle behind a kernel; the job's kernels and its
+//     copy-out go on the least-loaded compute stream, which first waits on
+//     the job's copy-in event.  Consecutive jobs thus overlap copy-in,
+//     compute and copy-out;
+//   - one completion thread per compute stream waits for that stream's jobs
+//     in order (a stream completes in order), returns their device memory,
+//     runs the callback and wakes waiters -- the asynchronous notification
+//     the paper adds on top of a runtime that only offers polling (Sec. 4.1).
 // Buffers are carved from one pinned host slab so copies never go through a
 // driver staging buffer (Sec. 2.1, Sec. 3).
 #include <algorithm>
@@ -103,12 +106,12 @@ struct Job {
     size_t need, dev_off;
     size_t in_region;
     int stream;
-    hipEvent_t ev;
     uint32_t seg_bytes;
     CdcParams cp;
     CdcGeom g;
     uint64_t cap;
     size_t d2h;
+    uint8_t *d_out_ptr = nullptr; // device bytes copied back
 };
 
 // Device bytes a job needs and the layout inside its region:
@@ -171,6 +174,22 @@ static bool plan_job(int kernel, size_t n, const void *params, Job *j, JobPlan *
     return true;
 }
 
+// Jobs dispatched together: their copy-ins go back to back on the copy-in
+// stream, then one compute stream runs their kernels -- direct-hashing jobs
+// of the same segment size share one segment launch and one root launch --
+// and their copy-outs, and one event marks the batch done.
+struct Batch {
+    std::vector<Job *> jobs;
+    int stream = 0;
+    hipEvent_t ev_in = nullptr, ev = nullptr;
+    int slot = -1; // job-table slot, when direct jobs were grouped
+};
+
+// Job-table slots: pinned host staging + device copy, one per batch in flight.
+constexpr uint32_t kMaxBatch = 32;
+constexpr size_t kSlotWords = 5 * (kMaxBatch + 1); // off, len, seg_base, out_off
+constexpr size_t kSlotBytes = 8 * kSlotWords;
+
 struct Lib {
     crystal_config cfg;
     int device = 0;
@@ -178,14 +197,17 @@ struct Lib {
     std::condition_variable cv_dispatch, cv_done, cv_pool;
     std::vector<std::unique_ptr<std::condition_variable>> cv_stream;
     std::deque<Job *> outstanding;
-    std::vector<std::deque<Job *>> running;
+    std::vector<std::deque<Batch *>> running;
     RangeAlloc dev_alloc, host_alloc;
     uint8_t *dev_slab = nullptr, *host_slab = nullptr;
     bool own_dev = false;
-    std::vector<hipStream_t> streams;
+    hipStream_t stream_in = nullptr; // copy-in stage
+    std::vector<hipStream_t> streams; // compute (+ copy-out) stages
     bool own_streams = false;
     std::vector<hipEvent_t> events;
     std::vector<hipEvent_t> free_events;
+    uint64_t *table_host = nullptr, *table_dev = nullptr;
+    std::vector<int> free_slots;
     std::set<crystal_buf *> bufs;
     std::thread dispatcher;
     std::vector<std::thread> completers;
@@ -235,65 +257,123 @@ static int pick_stream(Lib *L)
     return best;
 }
 
-// Enqueue copy-in, kernels, copy-out and the completion event.
-static hipError_t enqueue(Lib *L, Job *j)
+// Enqueue one batch: copy-ins (and the group's job table) on the copy-in
+// stream, an event there, and on the batch's compute stream: wait for that
+// event, kernels, copy-outs, the completion event.
+static hipError_t enqueue_batch(Lib *L, Batch *b)
 {
-    hipStream_t st = L->streams[j->stream];
-    uint8_t *base = L->dev_slab + j->dev_off;
-    uint8_t *d_in = base;
-    uint8_t *d_out = base + j->in_region;
+    hipStream_t st = L->streams[b->stream];
     hipError_t e = hipSuccess;
-    if (j->n) {
-        e = hipMemcpyAsync(d_in, j->in->host, j->n, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess)
-            return e;
+    for (Job *j : b->jobs) {
+        if (j->n && e == hipSuccess)
+            e = hipMemcpyAsync(L->dev_slab + j->dev_off, j->in->host, j->n,
+                               hipMemcpyHostToDevice, L->stream_in);
     }
-    switch (j->kernel) {
-    case CRYSTAL_K_NOP:
-        e = launch_nop(st);
-        d_out = d_in;
-        break;
-    case CRYSTAL_K_MD5:
-        e = launch_md5_whole(d_in, j->n, d_out, st);
-        break;
-    case CRYSTAL_K_MD5_DIRECT: {
-        JobTable jt{nullptr, nullptr, nullptr, 0, j->n};
-        const uint64_t nseg = (j->n + j->seg_bytes - 1) / j->seg_bytes;
-        e = launch_md5_segments(d_in, jt, j->seg_bytes, nseg, d_out, st);
-        if (e == hipSuccess)
-            e = launch_md5_roots(d_out, jt, j->seg_bytes, d_out + 16 * nseg, st);
-        break;
+    // direct-hashing jobs with the first such job's segment size run as one
+    // multi-job launch pair when there are at least two of them
+    std::vector<Job *> group;
+    for (Job *j : b->jobs)
+        if (j->kernel == CRYSTAL_K_MD5_DIRECT &&
+            (group.empty() || j->seg_bytes == group[0]->seg_bytes))
+            group.push_back(j);
+    if (group.size() < 2 || b->slot < 0)
+        group.clear();
+    uint64_t total_seg = 0;
+    uint64_t *dtab = nullptr;
+    if (!group.empty() && e == hipSuccess) {
+        const size_t G = group.size();
+        uint64_t *h = L->table_host + (size_t)b->slot * kSlotWords;
+        dtab = L->table_dev + (size_t)b->slot * kSlotWords;
+        uint64_t *h_off = h, *h_len = h + (kMaxBatch + 1), *h_base = h + 2 * (kMaxBatch + 1),
+                 *h_out = h + 3 * (kMaxBatch + 1);
+        for (size_t k = 0; k < G; k++) {
+            Job *j = group[k];
+            h_off[k] = j->dev_off;
+            h_len[k] = j->n;
+            h_base[k] = total_seg;
+            h_out[k] = j->dev_off + j->in_region;
+            total_seg += (j->n + j->seg_bytes - 1) / j->seg_bytes;
+        }
+        h_base[G] = total_seg;
+        e = hipMemcpyAsync(dtab, h, kSlotBytes, hipMemcpyHostToDevice, L->stream_in);
     }
-    case CRYSTAL_K_CDC: {
-        uint8_t *d_ws = d_out + al(j->d2h, 256);
-        uint64_t *cnt = reinterpret_cast<uint64_t *>(d_out);
-        uint64_t *ends = cnt + 1;
-        e = launch_cdc_candidates(d_in, j->g, j->cp, d_ws, st);
-        if (e == hipSuccess)
-            e = launch_cdc_select(j->g, j->cp, d_ws, cnt, ends, j->cap, st);
-        if (e == hipSuccess)
-            e = launch_md5_chunks(d_in, ends, cnt, j->cap, nullptr, st);
-        break;
-    }
-    }
+    if (e == hipSuccess)
+        e = hipEventRecord(b->ev_in, L->stream_in);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(st, b->ev_in, 0);
     if (e != hipSuccess)
         return e;
-    if (j->d2h) {
-        e = hipMemcpyAsync(j->out->host, d_out, j->d2h, hipMemcpyDeviceToHost, st);
+    if (!group.empty()) {
+        JobTable jt{dtab, dtab + (kMaxBatch + 1), dtab + 2 * (kMaxBatch + 1),
+                    (uint32_t)group.size(), 0, dtab + 3 * (kMaxBatch + 1)};
+        e = launch_md5_segments(L->dev_slab, jt, group[0]->seg_bytes, total_seg, L->dev_slab,
+                                st);
+        if (e == hipSuccess)
+            e = launch_md5_roots(L->dev_slab, jt, group[0]->seg_bytes, L->dev_slab, st);
         if (e != hipSuccess)
             return e;
     }
-    return hipEventRecord(j->ev, st);
+    for (Job *j : b->jobs) {
+        uint8_t *d_in = L->dev_slab + j->dev_off;
+        uint8_t *d_out = d_in + j->in_region;
+        bool grouped = std::find(group.begin(), group.end(), j) != group.end();
+        switch (j->kernel) {
+        case CRYSTAL_K_NOP:
+            e = launch_nop(st);
+            d_out = d_in;
+            break;
+        case CRYSTAL_K_MD5:
+            e = launch_md5_whole(d_in, j->n, d_out, st);
+            break;
+        case CRYSTAL_K_MD5_DIRECT: {
+            if (grouped)
+                break;
+            JobTable jt{nullptr, nullptr, nullptr, 0, j->n};
+            const uint64_t nseg = (j->n + j->seg_bytes - 1) / j->seg_bytes;
+            e = launch_md5_segments(d_in, jt, j->seg_bytes, nseg, d_out, st);
+            if (e == hipSuccess)
+                e = launch_md5_roots(d_out, jt, j->seg_bytes, d_out + 16 * nseg, st);
+            break;
+        }
+        case CRYSTAL_K_CDC: {
+            uint8_t *d_ws = d_out + al(j->d2h, 256);
+            uint64_t *cnt = reinterpret_cast<uint64_t *>(d_out);
+            uint64_t *ends = cnt + 1;
+            e = launch_cdc_candidates(d_in, j->g, j->cp, d_ws, st);
+            if (e == hipSuccess)
+                e = launch_cdc_select(j->g, j->cp, d_ws, cnt, ends, j->cap, st);
+            if (e == hipSuccess)
+                e = launch_md5_chunks(d_in, ends, cnt, j->cap, nullptr, st);
+            break;
+        }
+        }
+        if (e != hipSuccess)
+            return e;
+        j->d_out_ptr = d_out;
+    }
+    for (Job *j : b->jobs) {
+        if (j->d2h) {
+            e = hipMemcpyAsync(j->out->host, j->d_out_ptr, j->d2h, hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess)
+                return e;
+        }
+    }
+    return hipEventRecord(b->ev, st);
 }
 
-static void release_job_resources(Lib *L, Job *j)
+// Caller holds L->mu.
+static void release_batch_resources(Lib *L, Batch *b)
 {
-    // caller holds L->mu
-    L->dev_alloc.release(j->dev_off, j->need);
-    L->free_events.push_back(j->ev);
-    L->inflight--;
-    j->in->refs--;
-    j->out->refs--;
+    for (Job *j : b->jobs) {
+        L->dev_alloc.release(j->dev_off, j->need);
+        L->inflight--;
+        j->in->refs--;
+        j->out->refs--;
+    }
+    L->free_events.push_back(b->ev);
+    L->free_events.push_back(b->ev_in);
+    if (b->slot >= 0)
+        L->free_slots.push_back(b->slot);
 }
 
 static void dispatcher_main(Lib *L)
@@ -303,43 +383,62 @@ static void dispatcher_main(Lib *L)
     for (;;) {
         if (L->stop_dispatch)
             break;
-        if (L->outstanding.empty()) {
-            L->cv_dispatch.wait(lk);
+        // admit the FIFO head and as many following jobs as fit right now
+        Batch *b = new Batch;
+        while (!L->outstanding.empty() && b->jobs.size() < kMaxBatch) {
+            Job *j = L->outstanding.front();
+            size_t off = 0;
+            if (L->inflight >= L->cfg.max_in_flight || !L->dev_alloc.alloc(j->need, &off))
+                break;
+            L->outstanding.pop_front();
+            L->inflight++;
+            j->dev_off = off;
+            b->jobs.push_back(j);
+        }
+        if (b->jobs.empty()) {
+            delete b;
+            L->cv_dispatch.wait(lk); // new work or a completion frees room
             continue;
         }
-        Job *j = L->outstanding.front();
-        size_t off = 0;
-        if (L->inflight >= L->cfg.max_in_flight || L->free_events.empty() ||
-            !L->dev_alloc.alloc(j->need, &off)) {
-            L->cv_dispatch.wait(lk); // a completion frees room
-            continue;
-        }
-        L->outstanding.pop_front();
-        L->inflight++;
-        j->dev_off = off;
-        j->ev = L->free_events.back();
+        // batches <= jobs in flight, so the pools below always have entries
+        b->ev = L->free_events.back();
         L->free_events.pop_back();
-        j->stream = pick_stream(L);
-        j->t->stream_index = j->stream;
+        b->ev_in = L->free_events.back();
+        L->free_events.pop_back();
+        if (!L->free_slots.empty()) {
+            b->slot = L->free_slots.back();
+            L->free_slots.pop_back();
+        }
+        b->stream = pick_stream(L);
+        for (Job *j : b->jobs) {
+            j->stream = b->stream;
+            j->t->stream_index = b->stream;
+        }
         lk.unlock();
-        j->t->t_admit_ns = now_ns();
-        hipError_t e = enqueue(L, j);
+        const int64_t ta = now_ns();
+        for (Job *j : b->jobs)
+            j->t->t_admit_ns = ta;
+        hipError_t e = enqueue_batch(L, b);
         if (e != hipSuccess) {
-            // drain whatever was enqueued before releasing the region
-            (void)hipStreamSynchronize(L->streams[j->stream]);
+            // drain whatever was enqueued before releasing the regions
+            (void)hipStreamSynchronize(L->stream_in);
+            (void)hipStreamSynchronize(L->streams[b->stream]);
             set_error(CRYSTAL_EDEVICE, "job enqueue: %s", hipGetErrorString(e));
             lk.lock();
-            release_job_resources(L, j);
-            L->failed++;
+            release_batch_resources(L, b);
+            L->failed += b->jobs.size();
             lk.unlock();
-            finish_task(L, j->t, CRYSTAL_EDEVICE);
-            delete j;
+            for (Job *j : b->jobs) {
+                finish_task(L, j->t, CRYSTAL_EDEVICE);
+                delete j;
+            }
+            delete b;
             lk.lock();
             continue;
         }
         lk.lock();
-        L->running[j->stream].push_back(j);
-        L->cv_stream[j->stream]->notify_one();
+        L->running[b->stream].push_back(b);
+        L->cv_stream[b->stream]->notify_one();
     }
 }
 
@@ -354,37 +453,46 @@ static void completer_main(Lib *L, int s)
             L->cv_stream[s]->wait(lk);
             continue;
         }
-        Job *j = L->running[s].front();
+        Batch *b = L->running[s].front();
         lk.unlock();
-        hipError_t e = hipEventSynchronize(j->ev);
-        int status = CRYSTAL_OK;
-        size_t out_bytes = j->d2h;
-        if (e != hipSuccess) {
-            status = CRYSTAL_EDEVICE;
-            set_error(CRYSTAL_EDEVICE, "job execution: %s", hipGetErrorString(e));
-        } else if (j->kernel == CRYSTAL_K_CDC) {
-            uint64_t nc;
-            memcpy(&nc, j->out->host, 8);
-            if (nc > j->cap)
-                status = CRYSTAL_EDEVICE;
-            else
-                out_bytes = 8 + 24 * nc;
+        hipError_t e = hipEventSynchronize(b->ev);
+        std::vector<int> status(b->jobs.size(), CRYSTAL_OK);
+        for (size_t k = 0; k < b->jobs.size(); k++) {
+            Job *j = b->jobs[k];
+            size_t out_bytes = j->d2h;
+            if (e != hipSuccess) {
+                status[k] = CRYSTAL_EDEVICE;
+            } else if (j->kernel == CRYSTAL_K_CDC) {
+                uint64_t nc;
+                memcpy(&nc, j->out->host, 8);
+                if (nc > j->cap)
+                    status[k] = CRYSTAL_EDEVICE;
+                else
+                    out_bytes = 8 + 24 * nc;
+            }
+            j->t->out_bytes = status[k] == CRYSTAL_OK ? out_bytes : 0;
         }
-        j->t->out_bytes = status == CRYSTAL_OK ? out_bytes : 0;
+        if (e != hipSuccess)
+            set_error(CRYSTAL_EDEVICE, "job execution: %s", hipGetErrorString(e));
         lk.lock();
         L->running[s].pop_front();
-        release_job_resources(L, j);
-        if (status == CRYSTAL_OK) {
-            L->completed++;
-            L->bytes_in += j->n;
-            L->bytes_out += out_bytes;
-        } else {
-            L->failed++;
+        release_batch_resources(L, b);
+        for (size_t k = 0; k < b->jobs.size(); k++) {
+            if (status[k] == CRYSTAL_OK) {
+                L->completed++;
+                L->bytes_in += b->jobs[k]->n;
+                L->bytes_out += b->jobs[k]->t->out_bytes;
+            } else {
+                L->failed++;
+            }
         }
         lk.unlock();
         L->cv_dispatch.notify_one();
-        finish_task(L, j->t, status);
-        delete j;
+        for (size_t k = 0; k < b->jobs.size(); k++) {
+            finish_task(L, b->jobs[k]->t, status[k]);
+            delete b->jobs[k];
+        }
+        delete b;
         lk.lock();
     }
 }
@@ -421,7 +529,7 @@ int crystal_init(const crystal_config *cfg_in)
         return fail(CRYSTAL_EINVAL, "max_input_bytes must be > 0");
     crystal_config cfg = *cfg_in;
     if (cfg.n_streams == 0)
-        cfg.n_streams = 4;
+        cfg.n_streams = 3;
     if (cfg.n_streams > 64)
         return fail(CRYSTAL_EINVAL, "n_streams must be <= 64");
     if (cfg.max_in_flight == 0)
@@ -471,17 +579,18 @@ int crystal_init(const crystal_config *cfg_in)
     L->host_alloc.reset(cfg.host_pool_bytes);
     L->streams.resize(cfg.n_streams);
     if (cfg.streams) {
+        L->stream_in = static_cast<hipStream_t>(cfg.streams[0]);
         for (uint32_t s = 0; s < cfg.n_streams; s++)
-            L->streams[s] = static_cast<hipStream_t>(cfg.streams[s]);
+            L->streams[s] = static_cast<hipStream_t>(cfg.streams[s + 1]);
     } else {
         L->own_streams = true;
-        for (uint32_t s = 0; s < cfg.n_streams; s++) {
+        e = hipStreamCreateWithFlags(&L->stream_in, hipStreamNonBlocking);
+        for (uint32_t s = 0; s < cfg.n_streams && e == hipSuccess; s++)
             e = hipStreamCreateWithFlags(&L->streams[s], hipStreamNonBlocking);
-            if (e != hipSuccess)
-                return hip_fail(e, "hipStreamCreate");
-        }
+        if (e != hipSuccess)
+            return hip_fail(e, "hipStreamCreate");
     }
-    const uint32_t n_ev = cfg.max_in_flight + 1;
+    const uint32_t n_ev = 2 * (cfg.max_in_flight + 1);
     for (uint32_t i = 0; i < n_ev; i++) {
         hipEvent_t ev;
         e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -490,6 +599,14 @@ int crystal_init(const crystal_config *cfg_in)
         L->events.push_back(ev);
         L->free_events.push_back(ev);
     }
+    const uint32_t n_slots = cfg.max_in_flight + 1;
+    e = hipHostMalloc((void **)&L->table_host, n_slots * kSlotBytes, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&L->table_dev, n_slots * kSlotBytes);
+    if (e != hipSuccess)
+        return fail(CRYSTAL_ENOMEM, "job-table ring: %s", hipGetErrorString(e));
+    for (uint32_t i = 0; i < n_slots; i++)
+        L->free_slots.push_back((int)i);
     L->running.resize(cfg.n_streams);
     for (uint32_t s = 0; s < cfg.n_streams; s++)
         L->cv_stream.emplace_back(new std::condition_variable);
@@ -536,12 +653,16 @@ int crystal_finalize(void)
     (void)hipSetDevice(L->device);
     for (hipEvent_t ev : L->events)
         (void)hipEventDestroy(ev);
-    if (L->own_streams)
+    if (L->own_streams) {
+        (void)hipStreamDestroy(L->stream_in);
         for (hipStream_t s : L->streams)
             (void)hipStreamDestroy(s);
+    }
     if (L->own_dev)
         (void)hipFree(L->dev_slab);
     (void)hipHostFree(L->host_slab);
+    (void)hipHostFree(L->table_host);
+    (void)hipFree(L->table_dev);
     for (crystal_buf *b : L->bufs)
         delete b;
     g_lib = nullptr;

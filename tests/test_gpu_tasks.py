@@ -168,11 +168,14 @@ def test_overlapped_stream_of_jobs(lib, torch_cuda):
         assert P.crystal_wait(t) == 0
         _, er = oracle.direct(data)
         assert bytes(P.buffer_view(outb)[-16:]) == er
-    streams = {t.stream_index for t, _, _ in tasks}
-    assert len(streams) >= 2
+    # jobs waiting together are dispatched together (one copy-in run, one
+    # grouped kernel launch) or on different streams; either way their
+    # admitted-to-done intervals overlap
     iv = sorted((t.t_admit_ns, t.t_done_ns) for t, _, _ in tasks)
     overlaps = sum(1 for a, b in zip(iv, iv[1:]) if b[0] < a[1])
-    assert overlaps >= 1
+    assert overlaps >= n_jobs // 2
+    batches = len({(t.stream_index, t.t_admit_ns) for t, _, _ in tasks})
+    assert batches < n_jobs
     for b in bufs:
         P.crystal_buffer_release(b)
 
