@@ -1,0 +1,367 @@
+#!/usr/bin/env python3
+"""Measurements of the other four workloads on one MI355X (bench.py covers
+the streamed direct-hashing one).  Prints one JSON object per workload.
+
+  direct_one   1 MiB direct hashing as one job: per-job latency (mean, 95 %
+               CI, over >= 30 runs) through the job layer on one stream and
+               through the naive per-job path; device-resident kernel times.
+  chunking     256 MiB content-defined chunking (20 % repeated 64 KiB blocks):
+               device-resident time per kernel, and host-fed GB/s as one job
+               through the job layer vs the naive path.
+  serving      Poisson arrivals of jobs of 4 KiB..64 MiB (70 % direct, 30 %
+               chunking) from a 4 GiB pinned arena, device pool capped at
+               16 GiB, swept over offered loads: achieved GB/s, p50/p99/p99.9
+               latency from the scheduled arrival, admission wait.
+  batch        1 000 000 buffers of 512 B..16 KiB resident on the device:
+               tuned persistent plan (replay time, GB/s, integer-ALU and HBM
+               fractions) vs one launch per buffer (timed on a sample).
+
+Correctness is the test suite's job; this script only cross-checks GPU paths
+against each other.  Usage: python bench_workloads.py [--only NAME] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+OPS_PER_COMPRESSION = 64 * 5 + 4          # gfx950 VALU ops per MD5 block (see bench.py)
+INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBPS = 8000.0
+LINK_PEAK_GBPS = 63.0
+
+
+def ci95(xs):
+    xs = [float(x) for x in xs]
+    m = statistics.mean(xs)
+    if len(xs) < 2:
+        return m, 0.0
+    return m, 1.96 * statistics.stdev(xs) / math.sqrt(len(xs))
+
+
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
+
+
+def comp(length) -> int:
+    return (int(length) + 8) // 64 + 1
+
+
+def out(name, d):
+    d = {"workload": name, **d}
+    print(json.dumps(d), flush=True)
+    return d
+
+
+# ------------------------------------------------------------------ direct_one
+
+def direct_one(P, torch, gen, reps=50):
+    n = 1 << 20
+    data = gen.direct_one(n)
+    direct = P.crystal_direct_params(segment_bytes=4096)
+    cap = P.crystal_output_bytes(P.K_MD5_DIRECT, n, direct)
+    P.crystal_init(max_input_bytes=n, host_pool_bytes=16 << 20, device_pool_bytes=64 << 20,
+                   n_streams=1)
+    try:
+        inb = P.crystal_buffer_acquire(n)
+        P.buffer_view(inb)[:] = data
+        outb = P.crystal_buffer_acquire(cap)
+        lat, adm = [], []
+        for r in range(reps + 5):
+            t = P.new_task(n, direct)
+            P.crystal_submit(t, P.K_MD5_DIRECT, inb, outb)
+            assert P.crystal_wait(t) == 0
+            if r >= 5:
+                lat.append((t.t_done_ns - t.t_submit_ns) / 1e3)
+                adm.append((t.t_admit_ns - t.t_submit_ns) / 1e3)
+        job_root = bytes(P.buffer_view(outb)[cap - 16:cap])
+        P.crystal_buffer_release(inb)
+        P.crystal_buffer_release(outb)
+    finally:
+        P.crystal_finalize()
+    host = torch.from_numpy(data).pin_memory()
+    o = np.zeros(cap, np.uint8)
+    nv = []
+    for r in range(reps + 5):
+        _, st = P.crystal_naive_run(P.K_MD5_DIRECT, direct, host.data_ptr(), n, o, cap)
+        if r >= 5:
+            nv.append(st.total_ms * 1e3)
+    # device-resident kernel times
+    d, _ = P.to_device_bytes(data)
+    lens = np.array([n], np.uint64)
+    base = P.seg_table(lens)
+    tb = torch.from_numpy(base.view(np.int64)).cuda()
+    toff = torch.zeros(1, dtype=torch.int64, device="cuda")
+    tlen = torch.from_numpy(lens.view(np.int64)).cuda()
+    seg = torch.empty((256, 16), dtype=torch.uint8, device="cuda")
+    roots = torch.empty((1, 16), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    ks, kr = [], []
+    for r in range(reps + 5):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(s)
+        P.crystal_md5_segments_device(d, toff, tlen, tb, 1, 256, 4096, seg, s.cuda_stream)
+        e[1].record(s)
+        P.crystal_md5_roots_device(tb, 1, 4096, seg, roots, s.cuda_stream)
+        e[2].record(s)
+        e[2].synchronize()
+        if r >= 5:
+            ks.append(e[0].elapsed_time(e[1]) * 1e3)
+            kr.append(e[1].elapsed_time(e[2]) * 1e3)
+    m, c = ci95(lat)
+    nm, nc = ci95(nv)
+    return out("direct_one", {
+        "bytes": n, "runs": reps,
+        "job_latency_us": {"mean": round(m, 1), "ci95": round(c, 1), "p50": round(pct(lat, 50), 1),
+                           "p99": round(pct(lat, 99), 1)},
+        "job_admit_us_mean": round(statistics.mean(adm), 1),
+        "naive_latency_us": {"mean": round(nm, 1), "ci95": round(nc, 1),
+                             "p50": round(pct(nv, 50), 1)},
+        "speedup_vs_naive": round(nm / m, 2),
+        "device_kernels_us": {"segments": round(statistics.mean(ks), 1),
+                              "root": round(statistics.mean(kr), 1)},
+        "chain_bound_note": "65 + 65 serial compressions per lane plus 1 MiB over the link",
+        "job_root_matches_device": job_root == bytes(roots[0].cpu().numpy()),
+    })
+
+
+# -------------------------------------------------------------------- chunking
+
+def chunking(P, torch, gen, reps=10):
+    n = 256 << 20
+    base = gen.cdc_base()
+    params = P.cdc_params(base)
+    host = torch.empty(n, dtype=torch.uint8).pin_memory()
+    gen.cdc_input(out=host.numpy())
+    d = torch.empty(n + 256, dtype=torch.uint8, device="cuda")
+    d[:n].copy_(host)
+    ws_bytes = P.crystal_cdc_workspace_bytes(n, params)
+    cap = P.crystal_cdc_max_chunks(n, params)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ends = torch.empty(cap, dtype=torch.int64, device="cuda")
+    dig = torch.empty((cap, 16), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    tc, tsel, tch, tot = [], [], [], []
+    for r in range(reps + 2):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record(s)
+        P.crystal_cdc_candidates_device(d, n, params, ws, ws_bytes, None, None, 0, s.cuda_stream)
+        e[1].record(s)
+        P.crystal_cdc_select_device(n, params, ws, ws_bytes, cnt, ends, cap, s.cuda_stream)
+        e[2].record(s)
+        P.crystal_md5_chunks_device(d, ends, cnt, cap, dig, s.cuda_stream)
+        e[3].record(s)
+        e[3].synchronize()
+        if r >= 2:
+            tc.append(e[0].elapsed_time(e[1]))
+            tsel.append(e[1].elapsed_time(e[2]))
+            tch.append(e[2].elapsed_time(e[3]))
+            tot.append(e[0].elapsed_time(e[3]))
+    m = int(cnt.item())
+    lens = np.diff(np.concatenate([[0], ends[:m].cpu().numpy()]))
+    comps = int(sum(comp(x) for x in lens))
+    dev_ms = statistics.mean(tot)
+    # host-fed, one job through the job layer and through the naive path
+    outcap = P.crystal_output_bytes(P.K_CDC, n, params)
+    P.crystal_init(max_input_bytes=n, host_pool_bytes=64 << 20, device_pool_bytes=2 << 30,
+                   n_streams=2)
+    try:
+        outb = P.crystal_buffer_acquire(outcap)
+        inb = P.crystal_buffer_wrap(host.data_ptr(), n)
+        jt = []
+        for r in range(reps + 1):
+            t = P.new_task(n, params)
+            P.crystal_submit(t, P.K_CDC, inb, outb)
+            assert P.crystal_wait(t) == 0
+            if r >= 1:
+                jt.append((t.t_done_ns - t.t_submit_ns) / 1e6)
+        jends, jdig = P.parse_cdc_output(P.buffer_view(outb))
+        same = (np.array_equal(jends, ends[:m].cpu().numpy().view(np.uint64)) and
+                np.array_equal(jdig, dig[:m].cpu().numpy()))
+        P.crystal_buffer_release(inb)
+        P.crystal_buffer_release(outb)
+    finally:
+        P.crystal_finalize()
+    o = np.zeros(outcap, np.uint8)
+    nvt = []
+    for r in range(3):
+        _, st = P.crystal_naive_run(P.K_CDC, params, host.data_ptr(), n, o, outcap)
+        nvt.append(st.total_ms)
+    jm = statistics.mean(jt)
+    return out("chunking", {
+        "bytes": n, "chunks": m, "mean_chunk": round(n / m, 1), "candidates_per_MiB":
+            None, "compressions": comps,
+        "device_ms": {"candidates": round(statistics.mean(tc), 4),
+                      "select": round(statistics.mean(tsel), 4),
+                      "md5_chunks": round(statistics.mean(tch), 4),
+                      "total": round(dev_ms, 4)},
+        "device_gbps": round(n / 1e9 / (dev_ms / 1e3), 1),
+        "candidates_hbm_gbps": round(n / 1e9 / (statistics.mean(tc) / 1e3), 1),
+        "job_ms_mean": round(jm, 3), "job_gbps": round(n / 1e9 / (jm / 1e3), 2),
+        "naive_ms_mean": round(statistics.mean(nvt), 3),
+        "naive_gbps": round(n / 1e9 / (statistics.mean(nvt) / 1e3), 2),
+        "link_frac_job": round(n / 1e9 / (jm / 1e3) / LINK_PEAK_GBPS, 4),
+        "job_matches_device": bool(same),
+    })
+
+
+# --------------------------------------------------------------------- serving
+
+def serving(P, torch, gen, loads, n_jobs):
+    arena_bytes = 4 << 30
+    arena = torch.empty(arena_bytes, dtype=torch.uint8).pin_memory()
+    gen.fill(gen.sub_seed(gen.config_seed(4), 5), arena.data_ptr(), arena_bytes)
+    base = gen.cdc_base()
+    cdcp = P.cdc_params(base)
+    direct = P.crystal_direct_params(segment_bytes=4096)
+    spec0 = gen.serving_jobs(n_jobs=n_jobs, load_gbps=1.0, arena_bytes=arena_bytes)
+    caps = np.array([P.crystal_output_bytes(P.K_CDC if k else P.K_MD5_DIRECT, int(sz),
+                                            cdcp if k else direct)
+                     for sz, k in zip(spec0["size"], spec0["kind"])], dtype=np.int64)
+    ooff = np.zeros(n_jobs, dtype=np.int64)
+    ooff[1:] = np.cumsum((caps[:-1] + 255) // 256 * 256)
+    outs = torch.empty(int(ooff[-1] + caps[-1]), dtype=torch.uint8).pin_memory()
+    P.crystal_init(max_input_bytes=64 << 20, host_pool_bytes=16 << 20,
+                   device_pool_bytes=16 << 30, n_streams=2, max_in_flight=64)
+    results = []
+    try:
+        for load in loads:
+            spec = gen.serving_jobs(n_jobs=n_jobs, load_gbps=load, arena_bytes=arena_bytes)
+            jobs = (P.crystal_drive_job * n_jobs)()
+            for k in range(n_jobs):
+                kid = P.K_CDC if spec["kind"][k] else P.K_MD5_DIRECT
+                jobs[k].h_in = arena.data_ptr() + int(spec["offset"][k])
+                jobs[k].bytes = int(spec["size"][k])
+                jobs[k].h_out = outs.data_ptr() + int(ooff[k])
+                jobs[k].out_cap = int(caps[k])
+                jobs[k].arrival_s = float(spec["arrival_s"][k])
+                jobs[k].kernel_id = kid
+            stats0 = P.crystal_get_stats()
+            res = P.crystal_drive(jobs, direct, cdcp, window=0)
+            st = P.crystal_get_stats()
+            lat = np.array([jobs[k].latency_s for k in range(n_jobs)]) * 1e3
+            adm = np.array([jobs[k].admit_wait_s for k in range(n_jobs)]) * 1e3
+            offered_s = float(spec["arrival_s"][-1])
+            results.append({
+                "offered_gbps": load, "jobs": n_jobs, "ok": int(res.ok), "failed": int(res.failed),
+                "achieved_gbps": round(res.bytes / 1e9 / res.wall_s, 2),
+                "offered_span_s": round(offered_s, 3), "wall_s": round(res.wall_s, 3),
+                "p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3),
+                "p999_ms": round(pct(lat, 99.9), 3), "mean_ms": round(float(lat.mean()), 3),
+                "admit_wait_p50_ms": round(pct(adm, 50), 3),
+                "admit_wait_p99_ms": round(pct(adm, 99), 3),
+                "pool_min_free_gib": round(st.device_pool_min_free / 2 ** 30, 2),
+                "bytes": int(res.bytes), "completed_delta": int(st.completed - stats0.completed),
+            })
+            print(json.dumps({"serving_point": results[-1]}), flush=True)
+    finally:
+        P.crystal_finalize()
+    # operating point: highest load whose achieved rate is >= 95 % of offered
+    ok_pts = [r for r in results if r["achieved_gbps"] >= 0.95 * r["offered_gbps"]]
+    op = max(ok_pts, key=lambda r: r["offered_gbps"]) if ok_pts else None
+    return out("serving", {"points": results, "operating_point": op,
+                           "mean_job_bytes": float(spec0["size"].mean()),
+                           "device_pool_gib": 16})
+
+
+# ----------------------------------------------------------------------- batch
+
+def batch(P, torch, gen, n_buf, reps=20, sample_single=20000):
+    off, ln, arena_bytes, seed = gen.batch_small(n_buf=n_buf)
+    host = torch.empty(arena_bytes + 64, dtype=torch.uint8).pin_memory()
+    gen.fill(seed, host.data_ptr(), arena_bytes + 64)
+    d = host.to("cuda")
+    t_off = torch.from_numpy(off.view(np.int64)).cuda()
+    t_len = torch.from_numpy(ln.view(np.int32)).cuda()
+    o = torch.zeros((n_buf, 16), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    plan = P.crystal_batch_plan(d, t_off, t_len, n_buf, o, stream=s, tune=P._lib.TUNE_FULL)
+    plan_s = time.perf_counter() - t0
+    try:
+        tun = P.crystal_batch_get_tuning(plan)
+        times = []
+        for r in range(reps + 2):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            P.crystal_batch_run(plan, 1)
+            b.record(s)
+            b.synchronize()
+            if r >= 2:
+                times.append(a.elapsed_time(b))
+    finally:
+        P.crystal_batch_free(plan)
+    ms = statistics.mean(times)
+    total = int(ln.astype(np.int64).sum())
+    comps = int(((ln.astype(np.int64) + 8) // 64 + 1).sum())
+    ops = comps * OPS_PER_COMPRESSION
+    # one launch per buffer, timed on a sample and scaled to the whole batch
+    o2 = torch.zeros((n_buf, 16), dtype=torch.uint8, device="cuda")
+    lib = P.load()
+    ap, op_, lp, outp = d.data_ptr(), t_off.data_ptr(), t_len.data_ptr(), o2.data_ptr()
+    k = min(sample_single, n_buf)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for i in range(k):
+        lib.crystal_md5_batch_device(ap, op_ + 8 * i, lp + 4 * i, None, 1, outp + 16 * i, 64, 1,
+                                     s.cuda_stream)
+    s.synchronize()
+    single_s = (time.perf_counter() - ta) * n_buf / k
+    same = bool(torch.equal(o2[:k], o[:k]))
+    return out("batch", {
+        "buffers": n_buf, "bytes": total, "compressions": comps,
+        "tuning": {"block": tun.block, "waves_per_simd": tun.waves_per_simd, "grab": tun.grab,
+                   "streams": tun.n_streams, "sorted": tun.sorted,
+                   "tuned_replay_ms": round(tun.replay_ms, 4)},
+        "plan_seconds": round(plan_s, 2),
+        "replay_ms": round(ms, 4), "gbps": round(total / 1e9 / (ms / 1e3), 1),
+        "alu_tops": round(ops / (ms / 1e3) / 1e12, 2),
+        "alu_frac": round(ops / (ms / 1e3) / 1e12 / INT32_PEAK_TOPS, 4),
+        "hbm_frac": round(total / 1e9 / (ms / 1e3) / HBM_PEAK_GBPS, 4),
+        "one_launch_per_buffer_s_est": round(single_s, 3),
+        "one_launch_sample": k,
+        "speedup_vs_per_buffer": round(single_s / (ms / 1e3), 1),
+        "per_buffer_matches_plan": same,
+    })
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description="per-workload measurements")
+    ap.add_argument("--only", default="", help="comma list: direct_one,chunking,serving,batch")
+    ap.add_argument("--quick", action="store_true", help="fewer jobs / buffers")
+    ap.add_argument("--loads", default="5,10,20,30,40,45,50")
+    ap.add_argument("--serving-jobs", type=int, default=0)
+    ap.add_argument("--batch-buffers", type=int, default=0)
+    args = ap.parse_args()
+    import torch
+
+    import gen
+    import paper_1005_1695_amd as P
+    P.load()
+    torch.cuda.set_device(0)
+    only = set(x for x in args.only.split(",") if x)
+    want = lambda n: not only or n in only
+    if want("direct_one"):
+        direct_one(P, torch, gen)
+    if want("chunking"):
+        chunking(P, torch, gen)
+    if want("batch"):
+        batch(P, torch, gen, args.batch_buffers or (100_000 if args.quick else 1_000_000))
+    if want("serving"):
+        loads = [float(x) for x in args.loads.split(",")]
+        serving(P, torch, gen, loads, args.serving_jobs or (2000 if args.quick else 20000))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

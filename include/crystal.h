@@ -303,8 +303,10 @@ typedef struct crystal_batch_tuning {
     uint32_t waves_per_simd; /* persistent grid = 256 CUs x 4 SIMDs x this */
     uint32_t grab;           /* buffers a wave takes per work-counter grab,
                                 in units of 64 */
-    uint32_t n_streams;      /* parallel graph branches */
-    uint32_t sorted;         /* longest-first order */
+    uint32_t n_streams;      /* parallel branches (streams joined by events) */
+    uint32_t sorted;         /* lane order: 0 = index order, 1 = longest first
+                                over the whole batch, W > 1 = longest first
+                                within each run of W consecutive buffers */
     float replay_ms;         /* measured time of one replay */
 } crystal_batch_tuning;
 

@@ -21,6 +21,8 @@ struct crystal_batch {
     crystal_batch_desc d;
     int device;
     uint32_t n_simd;
+    std::vector<uint32_t> len;     // host copy of the lengths
+    uint32_t order_window = 0;     // sort window the device order holds
     uint32_t *d_order = nullptr;
     uint32_t *d_counters = nullptr;
     std::vector<uint64_t> work_prefix; // compressions, prefix over sorted order
@@ -44,6 +46,8 @@ static void destroy_graph(crystal_batch *b)
     b->graph = nullptr;
 }
 
+static hipError_t set_order(crystal_batch *b, uint32_t W);
+
 // Capture zero-counter + persistent kernel per branch.  Branch i covers a
 // contiguous slice of the order holding about 1/S of the total work.
 static hipError_t capture(crystal_batch *b, const crystal_batch_tuning &t)
@@ -56,7 +60,9 @@ static hipError_t capture(crystal_batch *b, const crystal_batch_tuning &t)
     if (grid == 0)
         grid = 1;
     const uint32_t *order = t.sorted ? b->d_order : nullptr;
-    hipError_t e = hipStreamBeginCapture(b->cap[0], hipStreamCaptureModeThreadLocal);
+    hipError_t e = t.sorted ? set_order(b, t.sorted) : hipSuccess;
+    if (e == hipSuccess)
+        e = hipStreamBeginCapture(b->cap[0], hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess)
         return e;
     if (S > 1) {
@@ -128,7 +134,19 @@ static hipError_t launch_direct(crystal_batch *b, const crystal_batch_tuning &t)
         grid = 1;
     const uint32_t *order = t.sorted ? b->d_order : nullptr;
     hipError_t e = hipSuccess;
-    if (S > 1) {
+    if (!t.sorted) { // work prefix of the index order
+        uint64_t acc = 0;
+        if (b->order_window != 0) {
+            for (uint64_t i = 0; i < n; i++) {
+                acc += (b->len[i] + 8) / 64 + 1;
+                b->work_prefix[i] = acc;
+            }
+            b->order_window = 0;
+        }
+    } else {
+        e = set_order(b, t.sorted);
+    }
+    if (S > 1 && e == hipSuccess) {
         e = hipEventRecord(b->ev[0], s0);
         for (uint32_t i = 1; i < S && e == hipSuccess; i++)
             e = hipStreamWaitEvent(b->cap[i], b->ev[0], 0);
@@ -167,6 +185,35 @@ static hipError_t launch_direct(crystal_batch *b, const crystal_batch_tuning &t)
                 e = hipStreamWaitEvent(s0, b->ev[i], 0);
         }
     }
+    return e;
+}
+
+// Lane order for a sort window W: W == 1 sorts the whole batch longest
+// first; W > 1 sorts longest first inside each run of W consecutive buffers,
+// so the 64 buffers a wave takes have nearly equal lengths (little lockstep
+// waste) and still lie close together in the arena.  Also rebuilds the work
+// prefix used to split the order across branches.
+static hipError_t set_order(crystal_batch *b, uint32_t W)
+{
+    if (W == 0 || W == b->order_window)
+        return hipSuccess;
+    const uint64_t n = b->d.n_buf;
+    std::vector<uint32_t> order(n);
+    std::iota(order.begin(), order.end(), 0u);
+    const uint64_t win = W == 1 ? n : W;
+    for (uint64_t lo = 0; lo < n; lo += win) {
+        const uint64_t hi = std::min<uint64_t>(n, lo + win);
+        std::stable_sort(order.begin() + lo, order.begin() + hi,
+                         [&](uint32_t x, uint32_t y) { return b->len[x] > b->len[y]; });
+    }
+    uint64_t acc = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        acc += (b->len[order[i]] + 8) / 64 + 1;
+        b->work_prefix[i] = acc;
+    }
+    hipError_t e = hipMemcpy(b->d_order, order.data(), 4 * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        b->order_window = W;
     return e;
 }
 
@@ -244,26 +291,20 @@ int crystal_batch_plan(const crystal_batch_desc *d, int tune_flags,
         return hip_fail(e, "hipGetDeviceProperties");
     }
     b->n_simd = (uint32_t)prop.multiProcessorCount * 4;
-    // longest-first order (ties by index) and the work prefix along it
-    std::vector<uint32_t> len(d->n_buf);
-    e = hipMemcpy(len.data(), d->d_len, 4 * d->n_buf, hipMemcpyDeviceToHost);
+    // lengths on the host: lane orders and the work prefix are built from them
+    b->len.resize(d->n_buf);
+    e = hipMemcpy(b->len.data(), d->d_len, 4 * d->n_buf, hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
         free_plan(b);
         return hip_fail(e, "reading lengths");
     }
-    std::vector<uint32_t> order(d->n_buf);
-    std::iota(order.begin(), order.end(), 0u);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t x, uint32_t y) { return len[x] > len[y]; });
     b->work_prefix.resize(d->n_buf);
     uint64_t acc = 0;
     for (uint64_t i = 0; i < d->n_buf; i++) {
-        acc += (len[order[i]] + 8) / 64 + 1;
+        acc += (b->len[i] + 8) / 64 + 1;
         b->work_prefix[i] = acc;
     }
     e = hipMalloc((void **)&b->d_order, 4 * d->n_buf);
-    if (e == hipSuccess)
-        e = hipMemcpy(b->d_order, order.data(), 4 * d->n_buf, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMalloc((void **)&b->d_counters, 4 * kMaxBranches);
     for (uint32_t i = 0; i < kMaxBranches && e == hipSuccess; i++)
@@ -276,7 +317,7 @@ int crystal_batch_plan(const crystal_batch_desc *d, int tune_flags,
     }
 
     std::vector<crystal_batch_tuning> cands;
-    crystal_batch_tuning def = {256, 4, 1, 1, 1, 0.f};
+    crystal_batch_tuning def = {256, 4, 1, 1, 4096, 0.f};
     if (fixed) {
         def = *fixed;
         if (def.block == 0)
@@ -293,10 +334,10 @@ int crystal_batch_plan(const crystal_batch_desc *d, int tune_flags,
         return fail(CRYSTAL_EINVAL, "bad tuning: block %% 64, <= 1024; streams <= 8");
     }
     if (tune_flags == CRYSTAL_TUNE_FULL) {
-        for (uint32_t sorted : {1u, 0u})
-            for (uint32_t S : {1u, 2u, 4u})
-                for (uint32_t blk : {64u, 256u, 1024u})
-                    for (uint32_t wps : {1u, 2u, 4u, 8u})
+        for (uint32_t sorted : {4096u, 65536u, 1u, 0u})
+            for (uint32_t S : {1u, 2u})
+                for (uint32_t blk : {64u, 256u})
+                    for (uint32_t wps : {2u, 4u, 8u})
                         for (uint32_t grab : {1u, 4u})
                             cands.push_back({blk, wps, grab, S, sorted, 0.f});
     } else {

@@ -9,6 +9,7 @@ namespace crystal {
 // Segment s of a launch: locate its job (multi-job launches search the
 // segment prefix table for the largest j with seg_base[j] <= s, which also
 // skips empty jobs), hash it, store its digest at index s.
+template <bool RING>
 __device__ __forceinline__ void md5_one_segment(const uint8_t *__restrict__ in,
                                                 const JobTable &jt, uint32_t seg_bytes,
                                                 uint64_t s, uint8_t *__restrict__ dig)
@@ -35,16 +36,26 @@ __device__ __forceinline__ void md5_one_segment(const uint8_t *__restrict__ in,
     const uint64_t n = rem < seg_bytes ? rem : seg_bytes;
     const uint8_t *p = in + off + start;
     uint32_t st[4];
-    if (((uintptr_t)p & 15) == 0)
-        md5_message_a16_pf(p, n, st);
-    else
-        md5_message_any(p, n, st);
+    if (((uintptr_t)p & 15) == 0) {
+        if (RING)
+            md5_message_a16_db<1>(p, n, st);
+        else
+            md5_message_a16_pf(p, n, st);
+    } else {
+        if (RING)
+            md5_message_any_db<2>(p, n, st);
+        else
+            md5_message_any(p, n, st);
+    }
     md5_store(dst, st);
 }
 
 // Grid-stride over segments: the host sizes the grid so every SIMD holds the
 // same number of waves and every lane the same number of segments, so no
 // partial last round of waves is left running on an otherwise idle chip.
+// RING: launches too small to give each SIMD a wave use the double-buffered
+// loader instead of one group of look-ahead.
+template <bool RING>
 __global__ __launch_bounds__(256) void k_md5_segments(const uint8_t *__restrict__ in,
                                                       JobTable jt, uint32_t seg_bytes,
                                                       uint64_t n_segments,
@@ -53,13 +64,13 @@ __global__ __launch_bounds__(256) void k_md5_segments(const uint8_t *__restrict_
     const uint64_t G = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n_segments;
          s += G)
-        md5_one_segment(in, jt, seg_bytes, s, dig);
+        md5_one_segment<RING>(in, jt, seg_bytes, s, dig);
 }
 
 // Lane j computes the root of job j: MD5 over its segment digests, which are
 // contiguous and 16-byte aligned in the digest array.  Each lane is one long
-// serial chain with few waves around it, so its loader keeps three 128-byte
-// groups in flight.  (Raising these waves' issue priority was measured to
+// serial chain with few waves around it, so its loader double-buffers two
+// 128-byte groups at a time.  (Raising these waves' issue priority was measured to
 // slow a concurrently running segment kernel by far more than it sped the
 // chains up, so they run at the default priority.)
 __global__ __launch_bounds__(64) void k_md5_roots(const uint8_t *__restrict__ dig,
@@ -84,7 +95,7 @@ __global__ __launch_bounds__(64) void k_md5_roots(const uint8_t *__restrict__ di
         dst = const_cast<uint8_t *>(src) + 16 * nseg;
     }
     uint32_t st[4];
-    md5_message_a16_ring<3>(src, 16 * nseg, st);
+    md5_message_a16_db<2>(src, 16 * nseg, st);
     md5_store(dst, st);
 }
 
@@ -95,9 +106,9 @@ __global__ __launch_bounds__(64) void k_md5_whole(const uint8_t *__restrict__ in
         return;
     uint32_t st[4];
     if (((uintptr_t)in & 15) == 0)
-        md5_message_a16(in, n, st);
+        md5_message_a16_db<2>(in, n, st);
     else
-        md5_message_any(in, n, st);
+        md5_message_any_db<2>(in, n, st);
     md5_store(out, st);
 }
 
@@ -110,7 +121,7 @@ __device__ __forceinline__ void md5_one_buffer(const uint8_t *__restrict__ arena
     const uint64_t l = len[m];
     uint32_t st[4];
     if (((uintptr_t)p & 15) == 0)
-        md5_message_a16(p, l, st);
+        md5_message_a16_pf(p, l, st);
     else
         md5_message_any(p, l, st);
     md5_store(out + 16 * m, st);
@@ -185,7 +196,7 @@ __global__ __launch_bounds__(256) void k_md5_chunks(const uint8_t *__restrict__ 
     const uint64_t lo = k ? ends[k - 1] : 0;
     const uint64_t hi = ends[k];
     uint32_t st[4];
-    md5_message_any(in + lo, hi - lo, st);
+    md5_message_any_db<2>(in + lo, hi - lo, st);
     if (dig) {
         md5_store(dig + 16 * k, st);
     } else {
@@ -243,8 +254,12 @@ hipError_t launch_md5_segments(const uint8_t *in, const JobTable &jt,
         const uint64_t per_lane = (n_segments + lanes_full - 1) / lanes_full;
         lanes = (n_segments + per_lane - 1) / per_lane;
     }
-    hipLaunchKernelGGL(k_md5_segments, dim3(blocks_for(lanes, 256)), dim3(256), 0, s, in,
-                       jt, seg_bytes, n_segments, seg_digests);
+    if (lanes < (uint64_t)device_simds() * 64)
+        hipLaunchKernelGGL(k_md5_segments<true>, dim3(blocks_for(lanes, 256)), dim3(256), 0,
+                           s, in, jt, seg_bytes, n_segments, seg_digests);
+    else
+        hipLaunchKernelGGL(k_md5_segments<false>, dim3(blocks_for(lanes, 256)), dim3(256), 0,
+                           s, in, jt, seg_bytes, n_segments, seg_digests);
     return hipGetLastError();
 }
 

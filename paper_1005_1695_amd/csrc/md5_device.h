@@ -199,10 +199,10 @@ __device__ __forceinline__ void md5_message_a16(const uint8_t *__restrict__ p,
     md5_finish(st, w, rb, len);
 }
 
-// Same digest as md5_message_a16, software-pipelined: the next 128 bytes are
-// requested before the current 128 bytes are compressed, so a lane keeps one
-// load group in flight behind its own compute.  Used where few waves share a
-// SIMD (long single chains, grids sized to the chip).
+// Same digest as md5_message_a16, software-pipelined one 128-byte group
+// ahead: the next group is requested before the current one is compressed.
+// Used by grids with several waves per SIMD, whose other waves cover most of
+// the load latency.
 __device__ __forceinline__ void md5_message_a16_pf(const uint8_t *__restrict__ p,
                                                    uint64_t len, uint32_t st[4])
 {
@@ -249,46 +249,84 @@ __device__ __forceinline__ void md5_message_a16_pf(const uint8_t *__restrict__ p
     md5_finish(st, w, rb, len);
 }
 
-// Same digest, with D groups of 128 bytes in flight per lane (a ring of D
-// register slots refilled as each is consumed).  For long chains that run
-// with few waves per SIMD, where one group of look-ahead does not cover the
-// load latency.
+// --- double-buffered loaders for chains that run with few waves per SIMD ---
+//
+// The message is consumed in chunks of D units.  Two register buffers
+// alternate: the loads for the other buffer are issued before the current
+// buffer is compressed, so each chunk's loads have a whole chunk of compute
+// to arrive.  The loop body is [load B | compress A | load A' | compress B];
+// the only wait that must be exact (before compressing B) sits inside one
+// basic block, and the wait the compiler places at the loop header finds
+// its loads already complete.  Look-ahead loads are unconditional, with the
+// chunk index clamped to the last full chunk (always inside the message).
+
 template <int D>
-__device__ __forceinline__ void md5_message_a16_ring(const uint8_t *__restrict__ p,
-                                                     uint64_t len, uint32_t st[4])
+__device__ __forceinline__ void a16_load_chunk(uint4 (&r)[D][8], const uint4 *q, uint64_t c)
 {
-    md5_init(st);
-    const uint4 *q = reinterpret_cast<const uint4 *>(p);
-    const uint64_t nb = len >> 6;
-    const uint64_t ng = nb >> 1; // whole 128-byte groups
-    const uint4 z = make_uint4(0, 0, 0, 0);
-    uint4 r[D][8];
+    const uint4 *b = q + (uint64_t)8 * D * c;
 #pragma unroll
     for (int j = 0; j < D; j++)
 #pragma unroll
         for (int k = 0; k < 8; k++)
-            r[j][k] = (uint64_t)j < ng ? q[8 * j + k] : z;
-    for (uint64_t g = 0; g < ng; g += D) {
+            r[j][k] = b[8 * j + k];
+}
+
+template <int D>
+__device__ __forceinline__ void a16_compress_chunk(uint32_t st[4], const uint4 (&r)[D][8])
+{
 #pragma unroll
-        for (int j = 0; j < D; j++) {
-            if (g + j < ng) {
-                uint32_t x[16];
-                md5_unpack4(x, r[j][0], r[j][1], r[j][2], r[j][3]);
-                md5_compress(st, x);
-                md5_unpack4(x, r[j][4], r[j][5], r[j][6], r[j][7]);
-                md5_compress(st, x);
-                if (g + j + D < ng) {
-                    const uint4 *n = q + 8 * (g + j + D);
-#pragma unroll
-                    for (int k = 0; k < 8; k++)
-                        r[j][k] = n[k];
-                }
-            }
-        }
+    for (int j = 0; j < D; j++) {
+        uint32_t x[16];
+        md5_unpack4(x, r[j][0], r[j][1], r[j][2], r[j][3]);
+        md5_compress(st, x);
+        md5_unpack4(x, r[j][4], r[j][5], r[j][6], r[j][7]);
+        md5_compress(st, x);
     }
+}
+
+// 16-byte-aligned message, chunks of D groups of 128 bytes.
+template <int D>
+__device__ __forceinline__ void md5_message_a16_db(const uint8_t *__restrict__ p,
+                                                   uint64_t len, uint32_t st[4])
+{
+    md5_init(st);
+    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+    const uint64_t nb = len >> 6;
+    const uint64_t ng = nb >> 1;
+    const uint64_t nc = ng / D;
+    if (nc) {
+        uint4 A[D][8], B[D][8];
+        a16_load_chunk<D>(A, q, 0);
+        uint64_t c = 0;
+        for (; c + 1 < nc; c += 2) {
+            // the barriers keep each chunk's loads ahead of the other
+            // chunk's compression (the scheduler would sink them)
+            a16_load_chunk<D>(B, q, c + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            a16_compress_chunk<D>(st, A);
+            __builtin_amdgcn_sched_barrier(0);
+            a16_load_chunk<D>(A, q, c + 2 < nc ? c + 2 : nc - 1);
+            __builtin_amdgcn_sched_barrier(0);
+            a16_compress_chunk<D>(st, B);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (c < nc) // odd chunk count: A holds chunk nc - 1
+            a16_compress_chunk<D>(st, A);
+    }
+    for (uint64_t g = nc * D; g < ng; ++g) {
+        const uint4 *r = q + 8 * g;
+        uint4 v0 = r[0], v1 = r[1], v2 = r[2], v3 = r[3];
+        uint4 v4 = r[4], v5 = r[5], v6 = r[6], v7 = r[7];
+        uint32_t x[16];
+        md5_unpack4(x, v0, v1, v2, v3);
+        md5_compress(st, x);
+        md5_unpack4(x, v4, v5, v6, v7);
+        md5_compress(st, x);
+    }
+    const uint4 z = make_uint4(0, 0, 0, 0);
     if (nb & 1) {
-        const uint4 *rr = q + 8 * ng;
-        uint4 v0 = rr[0], v1 = rr[1], v2 = rr[2], v3 = rr[3];
+        const uint4 *r = q + 8 * ng;
+        uint4 v0 = r[0], v1 = r[1], v2 = r[2], v3 = r[3];
         uint32_t x[16];
         md5_unpack4(x, v0, v1, v2, v3);
         md5_compress(st, x);
@@ -339,6 +377,101 @@ __device__ __forceinline__ void md5_message_any(const uint8_t *__restrict__ p,
 #pragma unroll
     for (int k = 0; k < 17; k++)
         u[k] = (uint32_t)k < span ? r[k] : 0u;
+    uint32_t w[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++)
+        w[k] = __builtin_amdgcn_alignbyte(u[k + 1], u[k], bs);
+    md5_finish(st, w, rb, len);
+}
+
+// Any-alignment message (see md5_message_any), double-buffered in chunks of
+// D blocks; each block slot holds the 17 dwords that cover it.  The extra
+// dword of a block is read from an index clamped to the dword holding the
+// message's last byte, so it stays readable even where it is not needed.
+template <int D>
+__device__ __forceinline__ void any_load_chunk(uint32_t (&r)[D][17], const uint32_t *d,
+                                               uint64_t c, uint64_t dmax)
+{
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        const uint64_t bi = (uint64_t)D * c + j;
+        const uint32_t *b = d + 16 * bi;
+        u32x4a4 v0 = *reinterpret_cast<const u32x4a4 *>(b);
+        u32x4a4 v1 = *reinterpret_cast<const u32x4a4 *>(b + 4);
+        u32x4a4 v2 = *reinterpret_cast<const u32x4a4 *>(b + 8);
+        u32x4a4 v3 = *reinterpret_cast<const u32x4a4 *>(b + 12);
+        const uint64_t e16 = 16 * bi + 16 < dmax ? 16 * bi + 16 : dmax;
+        r[j][0] = v0.x; r[j][1] = v0.y; r[j][2] = v0.z; r[j][3] = v0.w;
+        r[j][4] = v1.x; r[j][5] = v1.y; r[j][6] = v1.z; r[j][7] = v1.w;
+        r[j][8] = v2.x; r[j][9] = v2.y; r[j][10] = v2.z; r[j][11] = v2.w;
+        r[j][12] = v3.x; r[j][13] = v3.y; r[j][14] = v3.z; r[j][15] = v3.w;
+        r[j][16] = d[e16];
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void any_compress_chunk(uint32_t st[4], const uint32_t (&r)[D][17],
+                                                   uint32_t bs)
+{
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        uint32_t x[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            x[k] = __builtin_amdgcn_alignbyte(r[j][k + 1], r[j][k], bs);
+        md5_compress(st, x);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void md5_message_any_db(const uint8_t *__restrict__ p,
+                                                   uint64_t len, uint32_t st[4])
+{
+    md5_init(st);
+    const uint32_t bs = (uint32_t)((uintptr_t)p & 3);
+    const uint32_t *d = reinterpret_cast<const uint32_t *>(p - bs);
+    const uint64_t nb = len >> 6;
+    const uint64_t nc = nb / D;
+    const uint64_t dmax = len ? (bs + len - 1) >> 2 : 0; // dword holding the last byte
+    if (nc) {
+        uint32_t A[D][17], B[D][17];
+        any_load_chunk<D>(A, d, 0, dmax);
+        uint64_t c = 0;
+        for (; c + 1 < nc; c += 2) {
+            any_load_chunk<D>(B, d, c + 1, dmax);
+            __builtin_amdgcn_sched_barrier(0);
+            any_compress_chunk<D>(st, A, bs);
+            __builtin_amdgcn_sched_barrier(0);
+            any_load_chunk<D>(A, d, c + 2 < nc ? c + 2 : nc - 1, dmax);
+            __builtin_amdgcn_sched_barrier(0);
+            any_compress_chunk<D>(st, B, bs);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (c < nc)
+            any_compress_chunk<D>(st, A, bs);
+    }
+    for (uint64_t b = nc * D; b < nb; ++b) {
+        uint32_t r1[1][17];
+        const uint32_t *bb = d + 16 * b;
+        u32x4a4 v0 = *reinterpret_cast<const u32x4a4 *>(bb);
+        u32x4a4 v1 = *reinterpret_cast<const u32x4a4 *>(bb + 4);
+        u32x4a4 v2 = *reinterpret_cast<const u32x4a4 *>(bb + 8);
+        u32x4a4 v3 = *reinterpret_cast<const u32x4a4 *>(bb + 12);
+        const uint64_t e16 = 16 * b + 16 < dmax ? 16 * b + 16 : dmax;
+        r1[0][0] = v0.x; r1[0][1] = v0.y; r1[0][2] = v0.z; r1[0][3] = v0.w;
+        r1[0][4] = v1.x; r1[0][5] = v1.y; r1[0][6] = v1.z; r1[0][7] = v1.w;
+        r1[0][8] = v2.x; r1[0][9] = v2.y; r1[0][10] = v2.z; r1[0][11] = v2.w;
+        r1[0][12] = v3.x; r1[0][13] = v3.y; r1[0][14] = v3.z; r1[0][15] = v3.w;
+        r1[0][16] = d[e16];
+        any_compress_chunk<1>(st, r1, bs);
+    }
+    const uint32_t rb = (uint32_t)(len & 63);
+    const uint32_t *t = d + 16 * nb;
+    const uint32_t span = rb ? (bs + rb + 3) >> 2 : 0u;
+    uint32_t u[17];
+#pragma unroll
+    for (int k = 0; k < 17; k++)
+        u[k] = (uint32_t)k < span ? t[k] : 0u;
     uint32_t w[16];
 #pragma unroll
     for (int k = 0; k < 16; k++)
