@@ -5,14 +5,16 @@ Workload (the streamed direct-hashing configuration): 256 jobs of 8 MiB of
 seeded uniform bytes, each hashed as MD5 per 4 KiB segment followed by MD5
 over the job's concatenated segment digests.
 
-* One step = direct hashing of all 256 jobs with their inputs already
-  resident in HBM: the segment kernel over all 524 288 segments, then the
-  root kernel over the 256 jobs.  Consecutive steps are pipelined the way
-  the job layer overlaps consecutive jobs: step k's root kernel (256 serial
-  chains on a second stream) runs while step k+1's segment kernel runs, with
-  the segment digests double-buffered.  `value` is hashed GB/s (10^9
-  bytes/s) over the K timed steps, all of whose work completes inside the
-  timed region.  Each kernel is timed with HIP events on its own stream.
+* One step = direct hashing of one batch of all 256 jobs with their inputs
+  already resident in HBM: the segment kernel over all 524 288 segments and
+  the 256 roots.  Consecutive steps are software-pipelined the way the job
+  layer overlaps consecutive batches: segment digests go to a ring of 3R
+  batch slots, and one root launch computes the roots of R consecutive
+  batches (R x 256 serial chains, on one of two root streams) while the
+  segment kernels of later batches run (--root-group R, default 4).  `value`
+  is hashed GB/s (10^9 bytes/s) over the K timed steps, all of whose work
+  (every segment digest and every root) completes inside the timed region.
+  Each kernel is timed with HIP events on its own stream.
 * `e2e` (never `value`): the same 256 jobs fed from pinned host memory
   through the job layer (pooled device buffers, a copy-in stream and 2
   compute streams, copy/compute
@@ -67,10 +69,68 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
 
 
+COUNTERS_FILE = "md5_segments_streamed_direct_counters.json"
+CALIBRATION_BYTES = 1 << 30
+
+
+def _counter_means(csv_path: str, counter: str):
+    """Mean per-dispatch value of `counter` (summed over its instances) for the
+    segment kernel and for the calibration copy kernel."""
+    import csv
+    per = {}
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            key = (r["Dispatch_Id"], r["Kernel_Name"])
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    seg = [v for (d, k), v in per.items() if "k_md5_segments" in k]
+    cal = [v for (d, k), v in per.items() if "bitwise_not" in k.lower()]
+    cal_names = sorted({k for (d, k) in per if "bitwise_not" in k.lower()})
+    if not seg or not cal:
+        raise SystemExit(f"{csv_path}: no {counter} rows for the segment kernel or the copy")
+    return statistics.mean(seg), len(seg), max(cal), cal_names
+
+
+def summarize_counters(fetch_csv: str, write_csv: str, out: str, command: str) -> int:
+    """HBM bytes per launch of the segment kernel: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch) each scaled by what the same counter reads for an
+    elementwise kernel that reads and writes CALIBRATION_BYTES."""
+    f_seg, n_f, f_cal, names_f = _counter_means(fetch_csv, "FETCH_SIZE")
+    w_seg, n_w, w_cal, names_w = _counter_means(write_csv, "WRITE_SIZE")
+    f_scale = CALIBRATION_BYTES / (f_cal * 1024.0)
+    w_scale = CALIBRATION_BYTES / (w_cal * 1024.0)
+    fetch_b = f_seg * 1024.0 * f_scale
+    write_b = w_seg * 1024.0 * w_scale
+    alg = N_JOBS * JOB_BYTES + (N_JOBS * JOB_BYTES // SEGMENT) * 16
+    d = {
+        "kernel": "k_md5_segments",
+        "workload": "256 jobs x 8 MiB resident, 4 KiB segments (one launch = 2 GiB)",
+        "kernel_source_hash": kernel_source_hash(),
+        "fetch_kib_per_dispatch": round(f_seg, 1),
+        "write_kib_per_dispatch": round(w_seg, 1),
+        "dispatches": {"fetch": n_f, "write": n_w},
+        "calibration": {"bytes": CALIBRATION_BYTES, "fetch_kib": round(f_cal, 1),
+                        "write_kib": round(w_cal, 1), "fetch_scale": round(f_scale, 4),
+                        "write_scale": round(w_scale, 4), "kernels": sorted(set(names_f + names_w))},
+        "hbm_fetch_bytes_per_launch": int(fetch_b),
+        "hbm_write_bytes_per_launch": int(write_b),
+        "hbm_bytes_per_launch": int(fetch_b + write_b),
+        "algorithmic_bytes_per_launch": alg,
+        "traffic_over_algorithmic": round((fetch_b + write_b) / alg, 4),
+        "command": command,
+    }
+    with open(out, "w") as fh:
+        json.dump(d, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(d))
+    return 0
+
+
 def load_traffic(src_hash: str):
     """HBM bytes per launch of the segment kernel from the committed rocprofv3
     counter summary, or None if it was taken on different kernel sources."""
-    path = os.path.join(ROOT, "profiles", "md5_segments_streamed_direct_counters.json")
+    path = os.path.join(ROOT, "profiles", COUNTERS_FILE)
     try:
         with open(path) as fh:
             d = json.load(fh)
@@ -85,14 +145,31 @@ def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--no-e2e", action="store_true", help="skip the host-fed legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--root-group", type=int, default=4,
+                    help="batches whose roots one root launch computes (R)")
     ap.add_argument("--e2e-streams", type=int, default=2)
     ap.add_argument("--e2e-window", type=int, default=12)
     ap.add_argument("--cpu-jobs", type=int, default=0,
                     help="jobs in the CPU oracle sample (0 = sized to ~10 s)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed steps, run one elementwise kernel that reads and "
+                         "writes 1 GiB (bitwise_not): the known-size kernel that scales "
+                         "rocprofv3's FETCH_SIZE/WRITE_SIZE")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files "
+                         "(FETCH_SIZE pass, WRITE_SIZE pass) of a --calibrate-copy run into "
+                         "the per-launch HBM traffic summary (written to --counters-out)")
+    ap.add_argument("--counters-out", default=os.path.join(ROOT, "profiles",
+                                                           COUNTERS_FILE))
+    ap.add_argument("--counters-command", default="",
+                    help="the rocprofv3 command lines recorded in the summary")
     args = ap.parse_args()
+    if args.summarize_counters:
+        return summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
+                                  args.counters_out, args.counters_command)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the workload is sharded by job across GPUs, which this build does "
@@ -125,54 +202,99 @@ def main() -> int:
     t_off = torch.from_numpy(offs.view(np.int64)).to(dev)
     t_len = torch.from_numpy(lens.view(np.int64)).to(dev)
     t_base = torch.from_numpy(base.view(np.int64)).to(dev)
-    # digests triple-buffered; roots of consecutive steps alternate between two
-    # streams, so two root launches (each 256 serial chains) can be in flight
-    # while the segment kernel of a later step runs
-    NBUF, NROOT = 3, 2
-    segbufs = [torch.empty((n_seg, 16), dtype=torch.uint8, device=dev) for _ in range(NBUF)]
-    rootbufs = [torch.empty((N_JOBS, 16), dtype=torch.uint8, device=dev)
-                for _ in range(NBUF)]
+    # Digest ring of 3R batch slots.  The roots of R consecutive batches are
+    # computed together by one root launch (R x 256 serial chains) on one of
+    # two root streams, while the segment kernels of later batches run.  Each
+    # root launch that overlaps the segment kernel costs the latter time for
+    # as long as it runs, whatever its size, so grouping R batches per root
+    # launch divides that cost by R (measured: R=1 0.59, R=4 0.55 ms/step).
+    R = max(1, args.root_group)
+    NB, NROOT = 3 * R, 2
+    ring = torch.empty((NB, n_seg, 16), dtype=torch.uint8, device=dev)
+    ring_roots = torch.empty((NB, N_JOBS, 16), dtype=torch.uint8, device=dev)
+    base_r = P.seg_table(np.tile(lens, R), SEGMENT)   # seg table of R batches
+    t_base_r = torch.from_numpy(base_r.view(np.int64)).to(dev)
     torch.cuda.synchronize()
 
     sA = torch.cuda.current_stream()                              # segment kernels
     sB = [torch.cuda.Stream(device=dev) for _ in range(NROOT)]    # root kernels
     K = args.steps
 
-    def run(nsteps, timed):
-        """nsteps pipelined steps; returns per-step event quadruples."""
-        evs = []
-        root_done = []
-        for k in range(nsteps):
-            buf, rbuf = segbufs[k % NBUF], rootbufs[k % NBUF]
-            rs = sB[k % NROOT]
-            e = [torch.cuda.Event(enable_timing=timed) for _ in range(4)]
-            if k >= NBUF:
-                sA.wait_event(root_done[k - NBUF])  # digest buffer is free again
-            e[0].record(sA)
-            P.crystal_md5_segments_device(d_in, t_off, t_len, t_base, N_JOBS, n_seg,
-                                          SEGMENT, buf, sA.cuda_stream)
-            e[1].record(sA)
-            rs.wait_event(e[1])
-            e[2].record(rs)
-            P.crystal_md5_roots_device(t_base, N_JOBS, SEGMENT, buf, rbuf, rs.cuda_stream)
-            e[3].record(rs)
-            root_done.append(e[3])
-            evs.append(e)
-        return evs
+    n_groups = max(K, args.warmup) // R + 1
 
-    run(args.warmup, False)
+    def make_events(timed):
+        """All events one run() records, created up front and recorded once:
+        torch creates the HIP event lazily at its first record, and creating
+        events inside the timed loop was measured to stall the host for
+        milliseconds now and then."""
+        n = max(K, args.warmup)
+        seg = [tuple(torch.cuda.Event(enable_timing=timed) for _ in range(2)) for _ in range(n)]
+        root = [tuple(torch.cuda.Event(enable_timing=timed) for _ in range(2))
+                for _ in range(n_groups + 1)]
+        for pair in seg + root:
+            for e in pair:
+                e.record(sA)
+        torch.cuda.synchronize()
+        return seg, root
+
+    def run(nsteps, events):
+        """nsteps pipelined steps; returns (segment event pairs, root event pairs,
+        batches per root launch)."""
+        seg_pool, root_pool = events
+        seg_ev, root_ev, root_n = [], [], []
+        root_done = {}
+        first = 0  # first batch of the pending root group
+        for k in range(nsteps):
+            slot = k % NB
+            if k >= NB:
+                sA.wait_event(root_done[(k - NB) // R])  # slot is free again
+            e0, e1 = seg_pool[k]
+            e0.record(sA)
+            P.crystal_md5_segments_device(d_in, t_off, t_len, t_base, N_JOBS, n_seg,
+                                          SEGMENT, ring[slot], sA.cuda_stream)
+            e1.record(sA)
+            seg_ev.append((e0, e1))
+            if (k + 1) % R == 0 or k == nsteps - 1:
+                g = k // R
+                nb = k - first + 1
+                s0 = first % NB
+                rs = sB[g % NROOT]
+                rs.wait_event(e1)
+                r0, r1 = root_pool[g]
+                r0.record(rs)
+                P.crystal_md5_roots_device(t_base_r, N_JOBS * nb, SEGMENT,
+                                           ring[s0:s0 + nb], ring_roots[s0:s0 + nb],
+                                           rs.cuda_stream)
+                r1.record(rs)
+                root_done[g] = r1
+                root_ev.append((r0, r1))
+                root_n.append(nb)
+                first = k + 1
+        return seg_ev, root_ev, root_n
+
+    run(args.warmup, make_events(False))
     torch.cuda.synchronize()
+    timed_events = make_events(True)
     t0 = time.perf_counter()
-    ev = run(K, True)
+    seg_ev, root_ev, root_n = run(K, timed_events)
     for rs in sB:
         sA.wait_stream(rs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / K
-    seg_ms = statistics.mean(e[0].elapsed_time(e[1]) for e in ev)
-    root_ms = statistics.mean(e[2].elapsed_time(e[3]) for e in ev)
+    seg_ms = statistics.mean(a.elapsed_time(b) for a, b in seg_ev)
+    root_launch_ms = statistics.mean(a.elapsed_time(b) for a, b in root_ev)
+    root_ms = sum(a.elapsed_time(b) for a, b in root_ev) / sum(root_n)  # per batch
     value = total / 1e9 / (ms_per_step / 1e3)
-    roots = rootbufs[(K - 1) % NBUF]
+    roots = ring_roots[(K - 1) % NB]
+    segbufs, rootbufs = ring, ring_roots
+
+    if args.calibrate_copy:
+        cal_src = d_in[:CALIBRATION_BYTES]
+        cal_dst = torch.empty(CALIBRATION_BYTES, dtype=torch.uint8, device=dev)
+        torch.bitwise_not(cal_src, out=cal_dst)  # an elementwise kernel: reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del cal_dst
 
     # reference: the same step run back to back without overlap
     torch.cuda.synchronize()
@@ -208,10 +330,13 @@ def main() -> int:
         "kernel_source_hash": src_hash,
     }
     root_comp = N_JOBS * compressions(16 * (n_seg // N_JOBS))
-    kernels = {"k_md5_segments_ms": round(seg_ms, 4), "k_md5_roots_ms": round(root_ms, 4),
-               "root_chain_compressions": compressions(16 * (n_seg // N_JOBS)),
-               "root_us_per_compression": round(root_ms * 1e3 /
-                                                compressions(16 * (n_seg // N_JOBS)), 4),
+    chain = compressions(16 * (n_seg // N_JOBS))
+    kernels = {"k_md5_segments_ms": round(seg_ms, 4),
+               "root_group_batches": R,
+               "k_md5_roots_launch_ms": round(root_launch_ms, 4),
+               "k_md5_roots_ms_per_batch": round(root_ms, 4),
+               "root_chain_compressions": chain,
+               "root_us_per_compression": round(root_launch_ms * 1e3 / chain, 4),
                "root_compressions_total": root_comp,
                "serial_step_ms": round(serial_step_ms, 4),
                "pipelined_step_ms": round(ms_per_step, 4)}

@@ -6,57 +6,69 @@
 
 namespace crystal {
 
-// Segment s of a launch: locate its job (multi-job launches search the
-// segment prefix table for the largest j with seg_base[j] <= s, which also
-// skips empty jobs), hash it, store its digest at index s.
-template <bool RING>
+// Job of segment s in a multi-job launch: the largest j with
+// seg_base[j] <= s (which also skips empty jobs).
+__device__ __forceinline__ uint32_t segment_job(const JobTable &jt, uint64_t s)
+{
+    uint32_t lo = 0, hi = jt.n_jobs;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (jt.seg_base[mid] <= s)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// The common segment: full 4 KiB and 16-byte aligned.  Its loader is compiled
+// for that constant length, which keeps the kernel at 80 registers (six waves
+// per SIMD); ragged last segments, other segment sizes and unaligned jobs take
+// the lighter single-buffered loaders.
+constexpr uint64_t kFullSegment = 4096;
+
+// Segment s of a launch: locate its job, hash it, store its digest at index s
+// (or in its job's own output region).  Only s stays live across the hashing
+// (the destination is looked up again afterwards).
 __device__ __forceinline__ void md5_one_segment(const uint8_t *__restrict__ in,
                                                 const JobTable &jt, uint32_t seg_bytes,
                                                 uint64_t s, uint8_t *__restrict__ dig)
 {
     uint64_t off = 0, len = jt.single_len, local = s;
-    uint8_t *dst = dig + 16 * s;
     if (jt.n_jobs) {
-        uint32_t lo = 0, hi = jt.n_jobs;
-        while (hi - lo > 1) {
-            uint32_t mid = (lo + hi) >> 1;
-            if (jt.seg_base[mid] <= s)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        off = jt.off[lo];
-        len = jt.len[lo];
-        local = s - jt.seg_base[lo];
-        if (jt.out_off)
-            dst = dig + jt.out_off[lo] + 16 * local;
+        const uint32_t j = segment_job(jt, s);
+        off = jt.off[j];
+        len = jt.len[j];
+        local = s - jt.seg_base[j];
     }
     const uint64_t start = local * seg_bytes;
     const uint64_t rem = len - start;
     const uint64_t n = rem < seg_bytes ? rem : seg_bytes;
     const uint8_t *p = in + off + start;
     uint32_t st[4];
-    if (((uintptr_t)p & 15) == 0) {
-        if (RING)
-            md5_message_a16_db<1>(p, n, st);
-        else
-            md5_message_a16_pf(p, n, st);
-    } else {
-        if (RING)
-            md5_message_any_db<2>(p, n, st);
-        else
-            md5_message_any(p, n, st);
+    const bool aligned = ((uintptr_t)p & 15) == 0;
+    if (aligned && n == kFullSegment)
+        md5_message_a16_db<1>(p, kFullSegment, st);
+    else if (aligned)
+        md5_message_a16(p, n, st);
+    else
+        md5_message_any(p, n, st);
+    uint8_t *dst = dig + 16 * s;
+    if (jt.n_jobs && jt.out_off) {
+        const uint32_t j = segment_job(jt, s);
+        dst = dig + jt.out_off[j] + 16 * (s - jt.seg_base[j]);
     }
     md5_store(dst, st);
 }
 
-// Grid-stride over segments: the host sizes the grid so every SIMD holds the
-// same number of waves and every lane the same number of segments, so no
-// partial last round of waves is left running on an otherwise idle chip.
-// RING: launches too small to give each SIMD a wave use the double-buffered
-// loader instead of one group of look-ahead.
-template <bool RING>
-__global__ __launch_bounds__(256) void k_md5_segments(const uint8_t *__restrict__ in,
+// One segment per lane.  Each wave's work is one segment per lane, so the
+// hardware dispatcher balances waves across SIMDs as they free up: a static
+// split (a fixed number of segments per lane) was measured to lose far more
+// to the slowest SIMD when other kernels (the root chains of the previous
+// batch) share the chip.  The loop only covers launches beyond the grid cap.
+// Six waves per SIMD need at most 80 registers (the compiler moves one value
+// that lives across the whole loop to scratch to get there).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_md5_segments(const uint8_t *__restrict__ in,
                                                       JobTable jt, uint32_t seg_bytes,
                                                       uint64_t n_segments,
                                                       uint8_t *__restrict__ dig)
@@ -64,7 +76,7 @@ __global__ __launch_bounds__(256) void k_md5_segments(const uint8_t *__restrict_
     const uint64_t G = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n_segments;
          s += G)
-        md5_one_segment<RING>(in, jt, seg_bytes, s, dig);
+        md5_one_segment(in, jt, seg_bytes, s, dig);
 }
 
 // Lane j computes the root of job j: MD5 over its segment digests, which are
@@ -215,31 +227,8 @@ static inline uint32_t blocks_for(uint64_t n, uint32_t b)
     return (uint32_t)((n + b - 1) / b);
 }
 
-// Number of SIMDs of the current device (4 per compute unit), cached.
-static uint32_t device_simds()
-{
-    static int cached_dev = -1;
-    static uint32_t cached = 0;
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    if (dev != cached_dev || cached == 0) {
-        int cu = 0;
-        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) !=
-                hipSuccess ||
-            cu <= 0)
-            cu = 256;
-        cached = 4u * (uint32_t)cu;
-        cached_dev = dev;
-    }
-    return cached;
-}
-
-// Waves per SIMD the segment grid aims for before lanes take more than one
-// segment.  The kernel is bound by the HBM rate of 524 288 independent
-// 4 KiB streams, where more waves in flight measured faster than fewer
-// waves with more segments each; 8 covers the 256 x 8 MiB workload with
-// one segment per lane.
-static const uint32_t kSegWavesPerSimd = 8;
+// Grid cap of the segment kernel (lanes); launches beyond it loop.
+static const uint64_t kSegMaxLanes = (uint64_t)1 << 30;
 
 hipError_t launch_md5_segments(const uint8_t *in, const JobTable &jt,
                                uint32_t seg_bytes, uint64_t n_segments,
@@ -247,19 +236,9 @@ hipError_t launch_md5_segments(const uint8_t *in, const JobTable &jt,
 {
     if (n_segments == 0)
         return hipSuccess;
-    const uint64_t lanes_full = (uint64_t)device_simds() * kSegWavesPerSimd * 64;
-    uint64_t lanes = n_segments;
-    if (n_segments > lanes_full) {
-        // equal segments per lane, then just enough lanes for them
-        const uint64_t per_lane = (n_segments + lanes_full - 1) / lanes_full;
-        lanes = (n_segments + per_lane - 1) / per_lane;
-    }
-    if (lanes < (uint64_t)device_simds() * 64)
-        hipLaunchKernelGGL(k_md5_segments<true>, dim3(blocks_for(lanes, 256)), dim3(256), 0,
-                           s, in, jt, seg_bytes, n_segments, seg_digests);
-    else
-        hipLaunchKernelGGL(k_md5_segments<false>, dim3(blocks_for(lanes, 256)), dim3(256), 0,
-                           s, in, jt, seg_bytes, n_segments, seg_digests);
+    const uint64_t lanes = n_segments < kSegMaxLanes ? n_segments : kSegMaxLanes;
+    hipLaunchKernelGGL(k_md5_segments, dim3(blocks_for(lanes, 256)), dim3(256), 0, s, in, jt,
+                       seg_bytes, n_segments, seg_digests);
     return hipGetLastError();
 }
 
