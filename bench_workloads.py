@@ -153,7 +153,8 @@ def chunking(P, torch, gen, reps=10):
     s = torch.cuda.current_stream()
     tc, tsel, tch, tot = [], [], [], []
     for r in range(reps + 2):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        # the steps one by one (chunk digests in index order) ...
         e[0].record(s)
         P.crystal_cdc_candidates_device(d, n, params, ws, ws_bytes, None, None, 0, s.cuda_stream)
         e[1].record(s)
@@ -161,12 +162,16 @@ def chunking(P, torch, gen, reps=10):
         e[2].record(s)
         P.crystal_md5_chunks_device(d, ends, cnt, cap, dig, s.cuda_stream)
         e[3].record(s)
-        e[3].synchronize()
+        # ... and the whole pipeline (chunk digests longest first)
+        e[4].record(s)
+        P.crystal_cdc_device(d, n, params, ws, ws_bytes, cnt, ends, dig, cap, s.cuda_stream)
+        e[5].record(s)
+        e[5].synchronize()
         if r >= 2:
             tc.append(e[0].elapsed_time(e[1]))
             tsel.append(e[1].elapsed_time(e[2]))
             tch.append(e[2].elapsed_time(e[3]))
-            tot.append(e[0].elapsed_time(e[3]))
+            tot.append(e[4].elapsed_time(e[5]))
     m = int(cnt.item())
     lens = np.diff(np.concatenate([[0], ends[:m].cpu().numpy()]))
     comps = int(sum(comp(x) for x in lens))
@@ -203,8 +208,10 @@ def chunking(P, torch, gen, reps=10):
             None, "compressions": comps,
         "device_ms": {"candidates": round(statistics.mean(tc), 4),
                       "select": round(statistics.mean(tsel), 4),
-                      "md5_chunks": round(statistics.mean(tch), 4),
-                      "total": round(dev_ms, 4)},
+                      "md5_chunks_index_order": round(statistics.mean(tch), 4),
+                      "pipeline_total": round(dev_ms, 4),
+                      "order_and_md5_chunks": round(dev_ms - statistics.mean(tc) -
+                                                    statistics.mean(tsel), 4)},
         "device_gbps": round(n / 1e9 / (dev_ms / 1e3), 1),
         "candidates_hbm_gbps": round(n / 1e9 / (statistics.mean(tc) / 1e3), 1),
         "job_ms_mean": round(jm, 3), "job_gbps": round(n / 1e9 / (jm / 1e3), 2),

@@ -121,6 +121,11 @@ CdcGeom cdc_geometry(uint64_t n, const CdcParams &p)
     o = al256(o + 8);
     g.off_misc = o;
     o = al256(o + 64);
+    g.off_hist = o;
+    o = al256(o + 2 * 64 * 4);
+    g.ord_cap = n / p.min_len + 1;
+    g.off_ord = o;
+    o = al256(o + g.ord_cap * 4);
     g.total = o;
     return g;
 }
@@ -307,7 +312,7 @@ int crystal_md5_chunks_device(const void *d_in, const uint64_t *d_ends,
         return CRYSTAL_OK;
     if (!d_in || !d_ends || !d_n_chunks || !d_digests)
         return fail(CRYSTAL_EINVAL, "null pointer argument");
-    hipError_t e = launch_md5_chunks((const uint8_t *)d_in, d_ends, d_n_chunks, cap,
+    hipError_t e = launch_md5_chunks((const uint8_t *)d_in, d_ends, d_n_chunks, cap, nullptr,
                                      (uint8_t *)d_digests, (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(e, "md5_chunks launch");
@@ -325,7 +330,24 @@ int crystal_cdc_device(const void *d_in, uint64_t n, const crystal_cdc_params *p
     rc = crystal_cdc_select_device(n, p, d_ws, ws_bytes, d_n_chunks, d_ends, cap, stream);
     if (rc)
         return rc;
-    return crystal_md5_chunks_device(d_in, d_ends, d_n_chunks, cap, d_digests, stream);
+    if (cap == 0)
+        return CRYSTAL_OK;
+    if (!d_digests)
+        return fail(CRYSTAL_EINVAL, "null pointer argument");
+    CdcParams cp;
+    CdcGeom g;
+    rc = cdc_prepare(n, p, ws_bytes, &cp, &g); // validated by the steps above
+    if (rc)
+        return rc;
+    const uint32_t *order = nullptr;
+    hipError_t e = launch_chunk_order(g, (uint8_t *)d_ws, d_n_chunks, d_ends, cap, &order,
+                                      (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = launch_md5_chunks((const uint8_t *)d_in, d_ends, d_n_chunks, cap, order,
+                              (uint8_t *)d_digests, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "chunk order / md5_chunks launch");
+    return CRYSTAL_OK;
 }
 
 int crystal_window_hash_device(const void *d_in, uint64_t n, uint64_t base, uint64_t *d_w,

@@ -43,9 +43,10 @@ hipError_t launch_md5_batch_persistent(const uint8_t *arena, const uint64_t *off
                                        uint32_t grab, uint32_t block,
                                        uint32_t grid, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t s);
+// Digest of each chunk; lane i takes chunk order[i] (order == nullptr: chunk i).
 hipError_t launch_md5_chunks(const uint8_t *in, const uint64_t *ends,
                              const uint64_t *n_chunks, uint64_t cap,
-                             uint8_t *digests, hipStream_t s);
+                             const uint32_t *order, uint8_t *digests, hipStream_t s);
 hipError_t launch_nop(hipStream_t s);
 
 // ---------------------------------------------------------------- chunking
@@ -60,8 +61,9 @@ struct CdcGeom {
     uint64_t warm_bytes; // speculative warm-up D before each tile
     uint32_t n_tiles;
     uint32_t tile_cap;   // max chunk starts one tile can hold
+    uint64_t ord_cap;    // chunk order entries (the most chunks n bytes can hold)
     size_t off_l1, off_l2, off_cnt, off_rscan, off_exit, off_first, off_tcnt,
-        off_starts, off_toff, off_flags, off_bad, off_misc, total;
+        off_starts, off_toff, off_flags, off_bad, off_misc, off_hist, off_ord, total;
 };
 
 // Resolved parameters (defaults applied, validated).
@@ -81,6 +83,12 @@ hipError_t launch_cdc_compact(const CdcGeom &g, uint8_t *ws, uint64_t *d_count,
 hipError_t launch_cdc_select(const CdcGeom &g, const CdcParams &p, uint8_t *ws,
                              uint64_t *d_n_chunks, uint64_t *d_ends,
                              uint64_t cap, hipStream_t s);
+// Chunk order for the digest launch: chunk indices grouped into 1 KiB length
+// classes, longest class first (order inside a class unspecified).  Writes
+// ws + g.off_ord and returns that pointer in *order.
+hipError_t launch_chunk_order(const CdcGeom &g, uint8_t *ws, const uint64_t *d_n_chunks,
+                              const uint64_t *d_ends, uint64_t cap, const uint32_t **order,
+                              hipStream_t s);
 hipError_t launch_window_hash(const uint8_t *in, uint64_t n, uint64_t base,
                               uint64_t *w, hipStream_t s);
 

@@ -384,6 +384,88 @@ __global__ void k_store_zero_u64(uint64_t *p)
 
 // ---------------------------------------------------------------- launchers
 
+// ------------------------------------------------------------ chunk order
+// The chunk digests are one serial MD5 chain per chunk, and a wave runs as
+// long as its longest lane.  Handing chunks to lanes longest first (in 1 KiB
+// length classes) gives each wave 64 chains of nearly equal length and
+// starts the longest chains first: for 256 MiB of random input (26 K chunks,
+// the longest 1025 compressions) that measured 0.66 ms against 1.0 ms in
+// index order.  Counting sort: class histogram, scan, scatter.
+
+constexpr uint32_t kLenClasses = 64;
+
+// Class 0 holds the longest chunks (>= 63 KiB + 1 byte, also every longer
+// chunk when max_len exceeds 64 KiB), class 63 the shortest (<= 1 KiB).
+__device__ __forceinline__ uint32_t len_class(uint64_t len)
+{
+    const uint64_t c = len ? (len - 1) >> 10 : 0;
+    return kLenClasses - 1 - (uint32_t)(c < kLenClasses - 1 ? c : kLenClasses - 1);
+}
+
+__device__ __forceinline__ uint64_t chunk_len(const uint64_t *ends, uint64_t k)
+{
+    return ends[k] - (k ? ends[k - 1] : 0);
+}
+
+// One chunk per lane; per-workgroup class counts in LDS, added to hist.
+__global__ __launch_bounds__(256) void k_chunk_hist(const uint64_t *__restrict__ ends,
+                                                    const uint64_t *__restrict__ n_chunks,
+                                                    uint64_t cap, uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t h[kLenClasses];
+    if (threadIdx.x < kLenClasses)
+        h[threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t nc = *n_chunks;
+    nc = nc < cap ? nc : cap;
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nc)
+        atomicAdd(&h[len_class(chunk_len(ends, k))], 1u);
+    __syncthreads();
+    if (threadIdx.x < kLenClasses && h[threadIdx.x])
+        atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// hist[0..63] -> exclusive prefix in cursor[0..63] (one wave, serial in lane 0:
+// 64 entries).
+__global__ void k_chunk_class_scan(const uint32_t *__restrict__ hist,
+                                   uint32_t *__restrict__ cursor)
+{
+    if (threadIdx.x != 0)
+        return;
+    uint32_t acc = 0;
+    for (uint32_t c = 0; c < kLenClasses; c++) {
+        cursor[c] = acc;
+        acc += hist[c];
+    }
+}
+
+// One chunk per lane: a slot in its class, reserved per workgroup.
+__global__ __launch_bounds__(256) void k_chunk_scatter(const uint64_t *__restrict__ ends,
+                                                       const uint64_t *__restrict__ n_chunks,
+                                                       uint64_t cap, uint32_t *__restrict__ cursor,
+                                                       uint32_t *__restrict__ order)
+{
+    __shared__ uint32_t cnt[kLenClasses], base[kLenClasses];
+    if (threadIdx.x < kLenClasses)
+        cnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t nc = *n_chunks;
+    nc = nc < cap ? nc : cap;
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t cls = 0, local = 0;
+    if (k < nc) {
+        cls = len_class(chunk_len(ends, k));
+        local = atomicAdd(&cnt[cls], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kLenClasses && cnt[threadIdx.x])
+        base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (k < nc)
+        order[base[cls] + local] = (uint32_t)k;
+}
+
 static inline uint32_t nblk(uint64_t n, uint32_t b) { return (uint32_t)((n + b - 1) / b); }
 
 hipError_t launch_cdc_candidates(const uint8_t *in, const CdcGeom &g, const CdcParams &p,
@@ -462,6 +544,31 @@ hipError_t launch_cdc_select(const CdcGeom &g, const CdcParams &p, uint8_t *ws,
     hipLaunchKernelGGL(k_sel_emit, dim3(nblk(g.n_tiles, 64)), dim3(64), 0, s, a, toff, total,
                        d_n_chunks, d_ends, cap);
     e = hipGetLastError();
+    return e;
+}
+
+hipError_t launch_chunk_order(const CdcGeom &g, uint8_t *ws, const uint64_t *d_n_chunks,
+                              const uint64_t *d_ends, uint64_t cap, const uint32_t **order,
+                              hipStream_t s)
+{
+    *order = nullptr;
+    const uint64_t m = cap < g.ord_cap ? cap : g.ord_cap;
+    if (g.n == 0 || m == 0)
+        return hipSuccess;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ws + g.off_hist);
+    uint32_t *cursor = hist + kLenClasses;
+    uint32_t *ord = reinterpret_cast<uint32_t *>(ws + g.off_ord);
+    hipError_t e = launch_zero_u32(hist, kLenClasses, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_chunk_hist, dim3(nblk(m, 256)), dim3(256), 0, s, d_ends, d_n_chunks,
+                       m, hist);
+    hipLaunchKernelGGL(k_chunk_class_scan, dim3(1), dim3(64), 0, s, hist, cursor);
+    hipLaunchKernelGGL(k_chunk_scatter, dim3(nblk(m, 256)), dim3(256), 0, s, d_ends,
+                       d_n_chunks, m, cursor, ord);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+        *order = ord;
     return e;
 }
 

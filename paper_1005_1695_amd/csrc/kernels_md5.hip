@@ -189,22 +189,27 @@ __global__ void k_zero_u32(uint32_t *p, uint32_t n)
         p[i] = 0;
 }
 
-// Lane k hashes chunk [ends[k-1], ends[k]); chunk starts are arbitrary byte
-// offsets, so the realigning loader is used.  With dig == nullptr the
-// digests go right after the ends array (ends + n_chunks), the packed job
+// Lane i hashes chunk k = order[i] (k = i without an order), the bytes
+// [ends[k-1], ends[k]); chunk starts are arbitrary byte offsets, so the
+// realigning loader is used.  One wave per workgroup: these are long serial
+// chains, and single-wave groups let the dispatcher spread them over SIMDs
+// (four-wave groups put four chains' waves on one CU).  With dig == nullptr
+// the digests go right after the ends array (ends + n_chunks), the packed job
 // output layout; that address is only 8-byte aligned.
-__global__ __launch_bounds__(256) void k_md5_chunks(const uint8_t *__restrict__ in,
-                                                    const uint64_t *__restrict__ ends,
-                                                    const uint64_t *__restrict__ n_chunks,
-                                                    uint64_t cap,
-                                                    uint8_t *__restrict__ dig)
+__global__ __launch_bounds__(64) void k_md5_chunks(const uint8_t *__restrict__ in,
+                                                   const uint64_t *__restrict__ ends,
+                                                   const uint64_t *__restrict__ n_chunks,
+                                                   uint64_t cap,
+                                                   const uint32_t *__restrict__ order,
+                                                   uint8_t *__restrict__ dig)
 {
-    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t nc = *n_chunks;
     if (nc > cap)
         nc = cap;
-    if (k >= nc)
+    if (i >= nc)
         return;
+    const uint64_t k = order ? order[i] : i;
     const uint64_t lo = k ? ends[k - 1] : 0;
     const uint64_t hi = ends[k];
     uint32_t st[4];
@@ -294,12 +299,12 @@ hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t s)
 
 hipError_t launch_md5_chunks(const uint8_t *in, const uint64_t *ends,
                              const uint64_t *n_chunks, uint64_t cap,
-                             uint8_t *digests, hipStream_t s)
+                             const uint32_t *order, uint8_t *digests, hipStream_t s)
 {
     if (cap == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_md5_chunks, dim3(blocks_for(cap, 256)), dim3(256), 0, s,
-                       in, ends, n_chunks, cap, digests);
+    hipLaunchKernelGGL(k_md5_chunks, dim3(blocks_for(cap, 64)), dim3(64), 0, s,
+                       in, ends, n_chunks, cap, order, digests);
     return hipGetLastError();
 }
 

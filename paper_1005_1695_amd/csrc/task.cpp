@@ -342,8 +342,11 @@ static hipError_t enqueue_batch(Lib *L, Batch *b)
             e = launch_cdc_candidates(d_in, j->g, j->cp, d_ws, st);
             if (e == hipSuccess)
                 e = launch_cdc_select(j->g, j->cp, d_ws, cnt, ends, j->cap, st);
+            const uint32_t *order = nullptr;
             if (e == hipSuccess)
-                e = launch_md5_chunks(d_in, ends, cnt, j->cap, nullptr, st);
+                e = launch_chunk_order(j->g, d_ws, cnt, ends, j->cap, &order, st);
+            if (e == hipSuccess)
+                e = launch_md5_chunks(d_in, ends, cnt, j->cap, order, nullptr, st);
             break;
         }
         }
