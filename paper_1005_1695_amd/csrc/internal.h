@@ -49,6 +49,23 @@ hipError_t launch_md5_chunks(const uint8_t *in, const uint64_t *ends,
                              const uint32_t *order, uint8_t *digests, hipStream_t s);
 hipError_t launch_nop(hipStream_t s);
 
+// Chunking jobs of a batch whose chunk digests run in one chains launch.  All
+// offsets are bytes from the slab base; job j's output region holds
+// [u64 n][u64 ends[cap]...] and receives the packed digests after ends[n].
+constexpr uint64_t kNoOrder = ~0ull;
+struct ChainTable {
+    const uint64_t *in_off;  // input of job j
+    const uint64_t *out_off; // output region of job j
+    const uint64_t *ord_off; // chunk order (uint32 per lane), or kNoOrder
+    const uint64_t *cap;     // chunk capacity of job j
+    const uint64_t *lane0;   // n_jobs + 1 entries: first lane of job j (64-aligned)
+    uint32_t n_jobs;
+};
+// Roots of the direct group jt (outputs in the jobs' own regions, jt.out_off
+// set; jt.n_jobs may be 0) and the chunk digests of ct, one launch.
+hipError_t launch_md5_chains(uint8_t *slab, const JobTable &jt, uint32_t seg_bytes,
+                             const ChainTable &ct, uint64_t n_chunk_lanes, hipStream_t s);
+
 // ---------------------------------------------------------------- chunking
 // Byte range owned by one candidate lane; one bit-summary word per range.
 constexpr uint64_t kRangeBytes = 4096;

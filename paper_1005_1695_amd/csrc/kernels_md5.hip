@@ -85,14 +85,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 // 128-byte groups at a time.  (Raising these waves' issue priority was measured to
 // slow a concurrently running segment kernel by far more than it sped the
 // chains up, so they run at the default priority.)
-__global__ __launch_bounds__(64) void k_md5_roots(const uint8_t *__restrict__ dig,
-                                                  JobTable jt, uint32_t seg_bytes,
-                                                  uint8_t *__restrict__ roots)
+__device__ __forceinline__ void md5_root_of_job(const uint8_t *__restrict__ dig,
+                                                const JobTable &jt, uint32_t seg_bytes,
+                                                uint32_t j, uint8_t *__restrict__ roots)
 {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t nj = jt.n_jobs ? jt.n_jobs : 1;
-    if (j >= nj)
-        return;
     uint64_t b0 = 0, nseg;
     if (jt.n_jobs) {
         b0 = jt.seg_base[j];
@@ -109,6 +105,17 @@ __global__ __launch_bounds__(64) void k_md5_roots(const uint8_t *__restrict__ di
     uint32_t st[4];
     md5_message_a16_db<2>(src, 16 * nseg, st);
     md5_store(dst, st);
+}
+
+__global__ __launch_bounds__(64) void k_md5_roots(const uint8_t *__restrict__ dig,
+                                                  JobTable jt, uint32_t seg_bytes,
+                                                  uint8_t *__restrict__ roots)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nj = jt.n_jobs ? jt.n_jobs : 1;
+    if (j >= nj)
+        return;
+    md5_root_of_job(dig, jt, seg_bytes, j, roots);
 }
 
 __global__ __launch_bounds__(64) void k_md5_whole(const uint8_t *__restrict__ in,
@@ -189,13 +196,31 @@ __global__ void k_zero_u32(uint32_t *p, uint32_t n)
         p[i] = 0;
 }
 
-// Lane i hashes chunk k = order[i] (k = i without an order), the bytes
-// [ends[k-1], ends[k]); chunk starts are arbitrary byte offsets, so the
-// realigning loader is used.  One wave per workgroup: these are long serial
-// chains, and single-wave groups let the dispatcher spread them over SIMDs
-// (four-wave groups put four chains' waves on one CU).  With dig == nullptr
-// the digests go right after the ends array (ends + n_chunks), the packed job
-// output layout; that address is only 8-byte aligned.
+// Digest of chunk k, the bytes [ends[k-1], ends[k]); chunk starts are
+// arbitrary byte offsets, so the realigning loader is used.  With dig ==
+// nullptr the digest goes right after the ends array (ends + nc), the packed
+// job output layout; that address is only 8-byte aligned.
+__device__ __forceinline__ void md5_one_chunk(const uint8_t *__restrict__ in,
+                                              const uint64_t *__restrict__ ends, uint64_t nc,
+                                              uint64_t k, uint8_t *__restrict__ dig)
+{
+    const uint64_t lo = k ? ends[k - 1] : 0;
+    const uint64_t hi = ends[k];
+    uint32_t st[4];
+    md5_message_any_db<2>(in + lo, hi - lo, st);
+    if (dig) {
+        md5_store(dig + 16 * k, st);
+    } else {
+        uint64_t *q = const_cast<uint64_t *>(ends) + nc + 2 * k;
+        q[0] = (uint64_t)st[0] | ((uint64_t)st[1] << 32);
+        q[1] = (uint64_t)st[2] | ((uint64_t)st[3] << 32);
+    }
+}
+
+// Lane i hashes chunk order[i] (chunk i without an order).  One wave per
+// workgroup: these are long serial chains, and single-wave groups let the
+// dispatcher spread them over SIMDs (four-wave groups put four chains' waves
+// on one CU).
 __global__ __launch_bounds__(64) void k_md5_chunks(const uint8_t *__restrict__ in,
                                                    const uint64_t *__restrict__ ends,
                                                    const uint64_t *__restrict__ n_chunks,
@@ -209,18 +234,48 @@ __global__ __launch_bounds__(64) void k_md5_chunks(const uint8_t *__restrict__ i
         nc = cap;
     if (i >= nc)
         return;
-    const uint64_t k = order ? order[i] : i;
-    const uint64_t lo = k ? ends[k - 1] : 0;
-    const uint64_t hi = ends[k];
-    uint32_t st[4];
-    md5_message_any_db<2>(in + lo, hi - lo, st);
-    if (dig) {
-        md5_store(dig + 16 * k, st);
-    } else {
-        uint64_t *q = const_cast<uint64_t *>(ends) + nc + 2 * k;
-        q[0] = (uint64_t)st[0] | ((uint64_t)st[1] << 32);
-        q[1] = (uint64_t)st[2] | ((uint64_t)st[3] << 32);
+    md5_one_chunk(in, ends, nc, order ? order[i] : i, dig);
+}
+
+// The serial chains of a batch of jobs in one launch: lanes [0, jt.n_jobs)
+// compute the roots of a direct-hashing group (job table jt, outputs in each
+// job's own region), then each chunking job j owns the 64-aligned lane range
+// [lane0[j], lane0[j+1]) and its lane i hashes the job's chunk order[i] into
+// the packed output at out_off[j].  One launch runs all these chains side by
+// side, so a batch waits for its longest chain instead of the sum of its
+// jobs' longest chains.
+__global__ __launch_bounds__(64) void k_md5_chains(uint8_t *__restrict__ slab, JobTable jt,
+                                                   uint32_t seg_bytes, ChainTable ct)
+{
+    const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane < jt.n_jobs) {
+        md5_root_of_job(slab, jt, seg_bytes, (uint32_t)lane, slab);
+        return;
     }
+    if (ct.n_jobs == 0)
+        return;
+    const uint64_t l = lane - jt.n_jobs;
+    if (l >= ct.lane0[ct.n_jobs])
+        return;
+    uint32_t lo = 0, hi = ct.n_jobs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ct.lane0[mid] <= l)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const uint64_t i = l - ct.lane0[lo];
+    const uint64_t *ends = reinterpret_cast<const uint64_t *>(slab + ct.out_off[lo]) + 1;
+    uint64_t nc = ends[-1];
+    if (nc > ct.cap[lo])
+        nc = ct.cap[lo];
+    if (i >= nc)
+        return;
+    const uint64_t ord = ct.ord_off[lo];
+    const uint64_t k =
+        ord != kNoOrder ? reinterpret_cast<const uint32_t *>(slab + ord)[i] : i;
+    md5_one_chunk(slab + ct.in_off[lo], ends, nc, k, nullptr);
 }
 
 __global__ void k_nop() {}
@@ -305,6 +360,17 @@ hipError_t launch_md5_chunks(const uint8_t *in, const uint64_t *ends,
         return hipSuccess;
     hipLaunchKernelGGL(k_md5_chunks, dim3(blocks_for(cap, 64)), dim3(64), 0, s,
                        in, ends, n_chunks, cap, order, digests);
+    return hipGetLastError();
+}
+
+hipError_t launch_md5_chains(uint8_t *slab, const JobTable &jt, uint32_t seg_bytes,
+                             const ChainTable &ct, uint64_t n_chunk_lanes, hipStream_t s)
+{
+    const uint64_t lanes = jt.n_jobs + n_chunk_lanes;
+    if (lanes == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_md5_chains, dim3(blocks_for(lanes, 64)), dim3(64), 0, s, slab, jt,
+                       seg_bytes, ct);
     return hipGetLastError();
 }
 

@@ -175,19 +175,25 @@ static bool plan_job(int kernel, size_t n, const void *params, Job *j, JobPlan *
 }
 
 // Jobs dispatched together: their copy-ins go back to back on the copy-in
-// stream, then one compute stream runs their kernels -- direct-hashing jobs
-// of the same segment size share one segment launch and one root launch --
-// and their copy-outs, and one event marks the batch done.
+// stream, then one compute stream runs their kernels and their copy-outs, and
+// one event marks the batch done.  With a job-table slot, direct-hashing jobs
+// of the same segment size share one segment launch, and all serial chains
+// of the batch -- the roots of those direct jobs and the chunk digests of
+// every chunking job -- run in one chains launch, so the batch waits for its
+// longest chain rather than for the sum of its jobs' chains.
 struct Batch {
     std::vector<Job *> jobs;
     int stream = 0;
     hipEvent_t ev_in = nullptr, ev = nullptr;
-    int slot = -1; // job-table slot, when direct jobs were grouped
+    int slot = -1; // job-table slot
 };
 
 // Job-table slots: pinned host staging + device copy, one per batch in flight.
+// Arrays of kMaxBatch + 1 words: direct group off, len, seg_base, out_off;
+// chunking jobs in_off, out_off, ord_off, cap, lane0.
 constexpr uint32_t kMaxBatch = 32;
-constexpr size_t kSlotWords = 5 * (kMaxBatch + 1); // off, len, seg_base, out_off
+constexpr size_t kTabN = kMaxBatch + 1;
+constexpr size_t kSlotWords = 9 * kTabN;
 constexpr size_t kSlotBytes = 8 * kSlotWords;
 
 struct Lib {
@@ -257,7 +263,7 @@ static int pick_stream(Lib *L)
     return best;
 }
 
-// Enqueue one batch: copy-ins (and the group's job table) on the copy-in
+// Enqueue one batch: copy-ins (and the batch's job table) on the copy-in
 // stream, an event there, and on the batch's compute stream: wait for that
 // event, kernels, copy-outs, the completion event.
 static hipError_t enqueue_batch(Lib *L, Batch *b)
@@ -269,24 +275,26 @@ static hipError_t enqueue_batch(Lib *L, Batch *b)
             e = hipMemcpyAsync(L->dev_slab + j->dev_off, j->in->host, j->n,
                                hipMemcpyHostToDevice, L->stream_in);
     }
-    // direct-hashing jobs with the first such job's segment size run as one
-    // multi-job launch pair when there are at least two of them
-    std::vector<Job *> group;
-    for (Job *j : b->jobs)
-        if (j->kernel == CRYSTAL_K_MD5_DIRECT &&
-            (group.empty() || j->seg_bytes == group[0]->seg_bytes))
-            group.push_back(j);
-    if (group.size() < 2 || b->slot < 0)
-        group.clear();
-    uint64_t total_seg = 0;
+    // grouped work needs a table slot: direct jobs with the first direct
+    // job's segment size, and every chunking job
+    std::vector<Job *> group, cdc;
+    if (b->slot >= 0) {
+        for (Job *j : b->jobs) {
+            if (j->kernel == CRYSTAL_K_MD5_DIRECT &&
+                (group.empty() || j->seg_bytes == group[0]->seg_bytes))
+                group.push_back(j);
+            else if (j->kernel == CRYSTAL_K_CDC)
+                cdc.push_back(j);
+        }
+    }
+    uint64_t total_seg = 0, chunk_lanes = 0;
     uint64_t *dtab = nullptr;
-    if (!group.empty() && e == hipSuccess) {
-        const size_t G = group.size();
+    if ((!group.empty() || !cdc.empty()) && e == hipSuccess) {
         uint64_t *h = L->table_host + (size_t)b->slot * kSlotWords;
         dtab = L->table_dev + (size_t)b->slot * kSlotWords;
-        uint64_t *h_off = h, *h_len = h + (kMaxBatch + 1), *h_base = h + 2 * (kMaxBatch + 1),
-                 *h_out = h + 3 * (kMaxBatch + 1);
-        for (size_t k = 0; k < G; k++) {
+        uint64_t *h_off = h, *h_len = h + kTabN, *h_base = h + 2 * kTabN,
+                 *h_out = h + 3 * kTabN;
+        for (size_t k = 0; k < group.size(); k++) {
             Job *j = group[k];
             h_off[k] = j->dev_off;
             h_len[k] = j->n;
@@ -294,7 +302,23 @@ static hipError_t enqueue_batch(Lib *L, Batch *b)
             h_out[k] = j->dev_off + j->in_region;
             total_seg += (j->n + j->seg_bytes - 1) / j->seg_bytes;
         }
-        h_base[G] = total_seg;
+        h_base[group.size()] = total_seg;
+        uint64_t *c_in = h + 4 * kTabN, *c_out = h + 5 * kTabN, *c_ord = h + 6 * kTabN,
+                 *c_cap = h + 7 * kTabN, *c_lane0 = h + 8 * kTabN;
+        for (size_t k = 0; k < cdc.size(); k++) {
+            Job *j = cdc[k];
+            const size_t out_off = j->dev_off + j->in_region;
+            c_in[k] = j->dev_off;
+            c_out[k] = out_off;
+            // where launch_chunk_order leaves the order (it makes none for
+            // empty inputs)
+            const uint64_t m = j->cap < j->g.ord_cap ? j->cap : j->g.ord_cap;
+            c_ord[k] = (j->n && m) ? out_off + al(j->d2h, 256) + j->g.off_ord : kNoOrder;
+            c_cap[k] = j->cap;
+            c_lane0[k] = chunk_lanes;
+            chunk_lanes += al(j->cap, 64);
+        }
+        c_lane0[cdc.size()] = chunk_lanes;
         e = hipMemcpyAsync(dtab, h, kSlotBytes, hipMemcpyHostToDevice, L->stream_in);
     }
     if (e == hipSuccess)
@@ -303,20 +327,18 @@ static hipError_t enqueue_batch(Lib *L, Batch *b)
         e = hipStreamWaitEvent(st, b->ev_in, 0);
     if (e != hipSuccess)
         return e;
+    JobTable gjt{nullptr, nullptr, nullptr, 0, 0};
     if (!group.empty()) {
-        JobTable jt{dtab, dtab + (kMaxBatch + 1), dtab + 2 * (kMaxBatch + 1),
-                    (uint32_t)group.size(), 0, dtab + 3 * (kMaxBatch + 1)};
-        e = launch_md5_segments(L->dev_slab, jt, group[0]->seg_bytes, total_seg, L->dev_slab,
+        gjt = JobTable{dtab, dtab + kTabN, dtab + 2 * kTabN, (uint32_t)group.size(), 0,
+                       dtab + 3 * kTabN};
+        e = launch_md5_segments(L->dev_slab, gjt, group[0]->seg_bytes, total_seg, L->dev_slab,
                                 st);
-        if (e == hipSuccess)
-            e = launch_md5_roots(L->dev_slab, jt, group[0]->seg_bytes, L->dev_slab, st);
         if (e != hipSuccess)
             return e;
     }
     for (Job *j : b->jobs) {
         uint8_t *d_in = L->dev_slab + j->dev_off;
         uint8_t *d_out = d_in + j->in_region;
-        bool grouped = std::find(group.begin(), group.end(), j) != group.end();
         switch (j->kernel) {
         case CRYSTAL_K_NOP:
             e = launch_nop(st);
@@ -326,8 +348,8 @@ static hipError_t enqueue_batch(Lib *L, Batch *b)
             e = launch_md5_whole(d_in, j->n, d_out, st);
             break;
         case CRYSTAL_K_MD5_DIRECT: {
-            if (grouped)
-                break;
+            if (std::find(group.begin(), group.end(), j) != group.end())
+                break; // segments above, root in the chains launch
             JobTable jt{nullptr, nullptr, nullptr, 0, j->n};
             const uint64_t nseg = (j->n + j->seg_bytes - 1) / j->seg_bytes;
             e = launch_md5_segments(d_in, jt, j->seg_bytes, nseg, d_out, st);
@@ -345,7 +367,8 @@ static hipError_t enqueue_batch(Lib *L, Batch *b)
             const uint32_t *order = nullptr;
             if (e == hipSuccess)
                 e = launch_chunk_order(j->g, d_ws, cnt, ends, j->cap, &order, st);
-            if (e == hipSuccess)
+            const bool chained = std::find(cdc.begin(), cdc.end(), j) != cdc.end();
+            if (e == hipSuccess && !chained)
                 e = launch_md5_chunks(d_in, ends, cnt, j->cap, order, nullptr, st);
             break;
         }
@@ -353,6 +376,14 @@ static hipError_t enqueue_batch(Lib *L, Batch *b)
         if (e != hipSuccess)
             return e;
         j->d_out_ptr = d_out;
+    }
+    if (!group.empty() || !cdc.empty()) {
+        const ChainTable ct{dtab + 4 * kTabN, dtab + 5 * kTabN, dtab + 6 * kTabN,
+                            dtab + 7 * kTabN, dtab + 8 * kTabN, (uint32_t)cdc.size()};
+        e = launch_md5_chains(L->dev_slab, gjt, group.empty() ? 0 : group[0]->seg_bytes, ct,
+                              chunk_lanes, st);
+        if (e != hipSuccess)
+            return e;
     }
     for (Job *j : b->jobs) {
         if (j->d2h) {

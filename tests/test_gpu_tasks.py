@@ -233,6 +233,54 @@ def test_serving_mix_alone_equals_mix(lib, torch_cuda):
             assert mix[16 * len(es):16 * len(es) + 16].tobytes() == er, k
 
 
+def test_batched_chains_mixed_jobs(P, torch_cuda):
+    """Jobs submitted all at once are admitted together, so batches hold
+    several chunking and direct jobs whose roots and chunk digests run in one
+    chains launch; includes an empty and a 1-byte job of each kind, a ragged
+    direct job and chunking jobs with min_len 1 KiB.  Every output equals the
+    oracle's."""
+    torch = torch_cuda
+    P.crystal_init(max_input_bytes=4 << 20, host_pool_bytes=64 << 20,
+                   device_pool_bytes=1 << 30, n_streams=1, max_in_flight=32)
+    try:
+        rng = np.random.default_rng(77)
+        sizes = [0, 1, 0, 1, 4096 * 3 + 17] + [int(x) for x in
+                                                np.exp(rng.uniform(np.log(4096),
+                                                                   np.log(4 << 20), 43))]
+        kinds = [1, 1, 0, 0, 0] + [int(k) for k in rng.random(43) < 0.5]
+        n = len(sizes)
+        offs = np.zeros(n, dtype=np.int64)
+        offs[1:] = np.cumsum([(x + 4095) // 4096 * 4096 for x in sizes[:-1]])
+        arena = torch.empty(int(offs[-1]) + sizes[-1] + 4096, dtype=torch.uint8).pin_memory()
+        gen.fill(515, arena.data_ptr(), arena.numel())
+        base = gen.cdc_base()
+        jobs, outs, direct, _ = _drive_jobs(P, torch, sizes, kinds, [0.0] * n, arena, offs,
+                                            base)
+        cdcp = P.cdc_params(base, min_len=1024, max_len=16384, mask_bits=11)
+        for k in range(n):
+            if kinds[k]:
+                jobs[k].out_cap = P.crystal_output_bytes(P.K_CDC, sizes[k], cdcp)
+                outs[k] = torch.empty(jobs[k].out_cap, dtype=torch.uint8).pin_memory()
+                jobs[k].h_out = outs[k].data_ptr()
+        res = P.crystal_drive(jobs, direct, cdcp, window=0)
+        assert res.ok == n and res.failed == 0
+        a = arena.numpy()
+        for k in range(n):
+            data = a[int(offs[k]):int(offs[k]) + sizes[k]]
+            mix = outs[k].numpy()
+            if kinds[k]:
+                ends, dig = P.parse_cdc_output(mix)
+                ee, ed = oracle.cdc(data, base, min_len=1024, max_len=16384, mask_bits=11)
+                assert np.array_equal(ends, ee) and np.array_equal(dig, ed), k
+            else:
+                es, er = oracle.direct(data)
+                got = mix[:16 * len(es) + 16]
+                assert got[:16 * len(es)].tobytes() == es.tobytes(), k
+                assert got[16 * len(es):].tobytes() == er, k
+    finally:
+        P.crystal_finalize()
+
+
 def test_closed_loop_window(lib, torch_cuda):
     P, torch = lib, torch_cuda
     n = 24
