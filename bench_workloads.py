@@ -224,7 +224,7 @@ def chunking(P, torch, gen, reps=10):
 
 # --------------------------------------------------------------------- serving
 
-def serving(P, torch, gen, loads, n_jobs):
+def serving(P, torch, gen, loads, n_jobs, n_streams=3):
     arena_bytes = 4 << 30
     arena = torch.empty(arena_bytes, dtype=torch.uint8).pin_memory()
     gen.fill(gen.sub_seed(gen.config_seed(4), 5), arena.data_ptr(), arena_bytes)
@@ -239,7 +239,7 @@ def serving(P, torch, gen, loads, n_jobs):
     ooff[1:] = np.cumsum((caps[:-1] + 255) // 256 * 256)
     outs = torch.empty(int(ooff[-1] + caps[-1]), dtype=torch.uint8).pin_memory()
     P.crystal_init(max_input_bytes=64 << 20, host_pool_bytes=16 << 20,
-                   device_pool_bytes=16 << 30, n_streams=2, max_in_flight=64)
+                   device_pool_bytes=16 << 30, n_streams=n_streams, max_in_flight=64)
     results = []
     try:
         for load in loads:
@@ -278,7 +278,7 @@ def serving(P, torch, gen, loads, n_jobs):
     op = max(ok_pts, key=lambda r: r["offered_gbps"]) if ok_pts else None
     return out("serving", {"points": results, "operating_point": op,
                            "mean_job_bytes": float(spec0["size"].mean()),
-                           "device_pool_gib": 16})
+                           "device_pool_gib": 16, "compute_streams": n_streams})
 
 
 # ----------------------------------------------------------------------- batch
@@ -348,6 +348,7 @@ def main() -> int:
     ap.add_argument("--quick", action="store_true", help="fewer jobs / buffers")
     ap.add_argument("--loads", default="5,10,20,30,40,45,50")
     ap.add_argument("--serving-jobs", type=int, default=0)
+    ap.add_argument("--serving-streams", type=int, default=3)
     ap.add_argument("--batch-buffers", type=int, default=0)
     args = ap.parse_args()
     import torch
@@ -366,7 +367,8 @@ def main() -> int:
         batch(P, torch, gen, args.batch_buffers or (100_000 if args.quick else 1_000_000))
     if want("serving"):
         loads = [float(x) for x in args.loads.split(",")]
-        serving(P, torch, gen, loads, args.serving_jobs or (2000 if args.quick else 20000))
+        serving(P, torch, gen, loads, args.serving_jobs or (2000 if args.quick else 20000),
+                args.serving_streams)
     return 0
 
 
