@@ -140,7 +140,7 @@ __device__ __forceinline__ void md5_one_buffer(const uint8_t *__restrict__ arena
     const uint64_t l = len[m];
     uint32_t st[4];
     if (((uintptr_t)p & 15) == 0)
-        md5_message_a16_pf(p, l, st);
+        md5_message_a16_db<1>(p, l, st);
     else
         md5_message_any(p, l, st);
     md5_store(out + 16 * m, st);

@@ -199,57 +199,7 @@ __device__ __forceinline__ void md5_message_a16(const uint8_t *__restrict__ p,
     md5_finish(st, w, rb, len);
 }
 
-// Same digest as md5_message_a16, software-pipelined one 128-byte group
-// ahead: the next group is requested before the current one is compressed.
-// Used by grids with several waves per SIMD, whose other waves cover most of
-// the load latency.
-__device__ __forceinline__ void md5_message_a16_pf(const uint8_t *__restrict__ p,
-                                                   uint64_t len, uint32_t st[4])
-{
-    md5_init(st);
-    const uint4 *q = reinterpret_cast<const uint4 *>(p);
-    const uint64_t nb = len >> 6;
-    const uint64_t npairs = nb >> 1;
-    const uint4 z = make_uint4(0, 0, 0, 0);
-    uint4 c0 = z, c1 = z, c2 = z, c3 = z, c4 = z, c5 = z, c6 = z, c7 = z;
-    if (npairs) {
-        c0 = q[0]; c1 = q[1]; c2 = q[2]; c3 = q[3];
-        c4 = q[4]; c5 = q[5]; c6 = q[6]; c7 = q[7];
-    }
-    for (uint64_t k = 0; k < npairs; ++k) {
-        uint4 n0 = z, n1 = z, n2 = z, n3 = z, n4 = z, n5 = z, n6 = z, n7 = z;
-        if (k + 1 < npairs) {
-            const uint4 *r = q + 8 * (k + 1);
-            n0 = r[0]; n1 = r[1]; n2 = r[2]; n3 = r[3];
-            n4 = r[4]; n5 = r[5]; n6 = r[6]; n7 = r[7];
-        }
-        uint32_t x[16];
-        md5_unpack4(x, c0, c1, c2, c3);
-        md5_compress(st, x);
-        md5_unpack4(x, c4, c5, c6, c7);
-        md5_compress(st, x);
-        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
-        c4 = n4; c5 = n5; c6 = n6; c7 = n7;
-    }
-    if (nb & 1) {
-        const uint4 *r = q + 8 * npairs;
-        uint4 v0 = r[0], v1 = r[1], v2 = r[2], v3 = r[3];
-        uint32_t x[16];
-        md5_unpack4(x, v0, v1, v2, v3);
-        md5_compress(st, x);
-    }
-    const uint32_t rb = (uint32_t)(len & 63);
-    const uint4 *t = q + 4 * nb;
-    uint4 t0 = rb > 0 ? t[0] : z;
-    uint4 t1 = rb > 16 ? t[1] : z;
-    uint4 t2 = rb > 32 ? t[2] : z;
-    uint4 t3 = rb > 48 ? t[3] : z;
-    uint32_t w[16];
-    md5_unpack4(w, t0, t1, t2, t3);
-    md5_finish(st, w, rb, len);
-}
-
-// --- double-buffered loaders for chains that run with few waves per SIMD ---
+// --- double-buffered loaders ---
 //
 // The message is consumed in chunks of D units.  Two register buffers
 // alternate: the loads for the other buffer are issued before the current
