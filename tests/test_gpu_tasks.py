@@ -397,3 +397,76 @@ def test_batch_plan_fixed_multi_stream(P, torch_cuda):
                 assert np.array_equal(out.cpu().numpy(), exp)
         finally:
             P.crystal_batch_free(plan)
+
+
+def test_batch_plan_full_size_sampled(P, torch_cuda):
+    """The batched small-buffer workload at full size (10^6 buffers of
+    log-uniform 512 B..16 KiB, 4.58 GB), with the tuned plan the workload
+    benchmark times: 4000 sampled digests (and the longest and shortest
+    buffers) equal the oracle's."""
+    torch = torch_cuda
+    off, ln, arena, seed = gen.batch_small()
+    host = torch.empty(arena + 64, dtype=torch.uint8).pin_memory()
+    gen.fill(seed, host.data_ptr(), arena + 64)
+    d = host.to("cuda")
+    t_off = torch.from_numpy(off.view(np.int64)).cuda()
+    t_len = torch.from_numpy(ln.view(np.int32)).cuda()
+    n = len(ln)
+    out = torch.zeros((n, 16), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    plan = P.crystal_batch_plan(d, t_off, t_len, n, out, stream=s, tune=P._lib.TUNE_FULL)
+    try:
+        with torch.cuda.stream(s):
+            out.zero_()
+            P.crystal_batch_run(plan, 1)
+        s.synchronize()
+    finally:
+        P.crystal_batch_free(plan)
+    got = out.cpu().numpy()
+    hv = host.numpy()
+    rng = np.random.default_rng(5)
+    pick = set(rng.choice(n, 4000, replace=False).tolist())
+    pick |= {int(np.argmax(ln)), int(np.argmin(ln)), 0, n - 1}
+    for m in sorted(pick):
+        o, L = int(off[m]), int(ln[m])
+        assert got[m].tobytes() == oracle.md5(hv[o:o + L]), m
+
+
+def test_serving_mix_large_jobs_sampled(P, torch_cuda):
+    """Open-loop mix with the full size range (4 KiB..64 MiB, 70 % direct /
+    30 % chunking) through a 16 GiB pool at 40 GB/s offered: all jobs finish,
+    and a sample that includes the largest jobs of each kind equals the
+    oracle."""
+    torch = torch_cuda
+    n = 400
+    spec = gen.serving_jobs(n_jobs=n, load_gbps=40.0, arena_bytes=1 << 30, seed=9090)
+    arena = torch.empty(spec["arena_bytes"], dtype=torch.uint8).pin_memory()
+    gen.fill(spec["arena_seed"], arena.data_ptr(), spec["arena_bytes"])
+    base = gen.cdc_base()
+    P.crystal_init(max_input_bytes=64 << 20, host_pool_bytes=16 << 20,
+                   device_pool_bytes=16 << 30, n_streams=3, max_in_flight=64)
+    try:
+        jobs, outs, direct, cdcp = _drive_jobs(P, torch, spec["size"], spec["kind"],
+                                               spec["arrival_s"], arena, spec["offset"], base)
+        res = P.crystal_drive(jobs, direct, cdcp, window=0)
+        assert res.ok == n and res.failed == 0
+    finally:
+        P.crystal_finalize()
+    a = arena.numpy()
+    sizes, kinds = np.asarray(spec["size"]), np.asarray(spec["kind"])
+    pick = set(np.random.default_rng(3).choice(n, 24, replace=False).tolist())
+    for kind in (0, 1):
+        idx = np.flatnonzero(kinds == kind)
+        pick |= set(idx[np.argsort(sizes[idx])[-3:]].tolist())
+    for k in sorted(pick):
+        sz, of = int(sizes[k]), int(spec["offset"][k])
+        data = a[of:of + sz]
+        mix = outs[k].numpy()
+        if kinds[k]:
+            ends, dig = P.parse_cdc_output(mix)
+            ee, ed = oracle.cdc(data, base)
+            assert np.array_equal(ends, ee) and np.array_equal(dig, ed), k
+        else:
+            es, er = oracle.direct(data)
+            assert mix[:16 * len(es)].tobytes() == es.tobytes(), k
+            assert mix[16 * len(es):16 * len(es) + 16].tobytes() == er, k
