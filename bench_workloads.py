@@ -12,6 +12,10 @@ the streamed direct-hashing one).  Prints one JSON object per workload.
                chunking) from a 4 GiB pinned arena, device pool capped at
                16 GiB, swept over offered loads: achieved GB/s, p50/p99/p99.9
                latency from the scheduled arrival, admission wait.
+  overhead     framework overhead per job with an empty kernel, by size
+               (job layer vs naive path vs the copies alone).
+  naive_stages stage breakdown of the naive direct-hashing path by size.
+  stream_len   streams of 1..64 jobs of 1 MiB: job layer vs naive path.
   batch        1 000 000 buffers of 512 B..16 KiB resident on the device:
                tuned persistent plan (replay time, GB/s, integer-ALU and HBM
                fractions) vs one launch per buffer (timed on a sample).
@@ -132,6 +136,135 @@ def direct_one(P, torch, gen, reps=50):
         "chain_bound_note": "65 + 65 serial compressions per lane plus 1 MiB over the link",
         "job_root_matches_device": job_root == bytes(roots[0].cpu().numpy()),
     })
+
+
+# -------------------------------------------------------------------- overhead
+
+def overhead(P, torch, gen, reps=30, sizes=(4 << 10, 64 << 10, 1 << 20, 8 << 20, 64 << 20)):
+    """Framework overhead per job (the paper's Sec. 5.1 dummy kernel, Fig. 5):
+    one job at a time that copies n bytes in, runs an empty kernel and copies n
+    bytes back, through the job layer and through the naive path; overhead =
+    job latency minus the two pinned copies timed alone."""
+    rows = []
+    P.crystal_init(max_input_bytes=max(sizes), host_pool_bytes=2 * max(sizes) + (64 << 20),
+                   device_pool_bytes=2 * max(sizes) + (64 << 20), n_streams=1)
+    try:
+        dev = torch.empty(max(sizes), dtype=torch.uint8, device="cuda")
+        hbuf = torch.empty(max(sizes), dtype=torch.uint8).pin_memory()
+        for n in sizes:
+            inb = P.crystal_buffer_acquire(n)
+            outb = P.crystal_buffer_acquire(n)
+            P.buffer_view(inb)[:] = gen.random_bytes(n + 11, n)
+            lat = []
+            for r in range(reps + 3):
+                t = P.new_task(n, None)
+                P.crystal_submit(t, P.K_NOP, inb, outb)
+                assert P.crystal_wait(t) == 0
+                if r >= 3:
+                    lat.append((t.t_done_ns - t.t_submit_ns) / 1e3)
+            assert bytes(P.buffer_view(outb)[:64]) == bytes(P.buffer_view(inb)[:64])
+            P.crystal_buffer_release(inb)
+            P.crystal_buffer_release(outb)
+            cp = []
+            for r in range(reps + 3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                dev[:n].copy_(hbuf[:n], non_blocking=True)
+                hbuf[:n].copy_(dev[:n], non_blocking=True)
+                torch.cuda.synchronize()
+                if r >= 3:
+                    cp.append((time.perf_counter() - t0) * 1e6)
+            o = np.zeros(n, np.uint8)
+            nv, alloc, free = [], [], []
+            for r in range(min(reps, 10) + 2):
+                _, st = P.crystal_naive_run(P.K_NOP, None, hbuf.data_ptr(), n, o, n)
+                if r >= 2:
+                    nv.append(st.total_ms * 1e3)
+                    alloc.append(st.alloc_ms * 1e3)
+                    free.append(st.free_ms * 1e3)
+            m, c = ci95(lat)
+            cm, _ = ci95(cp)
+            nm, nc = ci95(nv)
+            rows.append({"bytes": n, "job_us": round(m, 1), "job_ci95_us": round(c, 1),
+                         "copies_alone_us": round(cm, 1),
+                         "framework_overhead_us": round(m - cm, 1),
+                         "naive_us": round(nm, 1), "naive_ci95_us": round(nc, 1),
+                         "naive_alloc_us": round(statistics.mean(alloc), 1),
+                         "naive_free_us": round(statistics.mean(free), 1)})
+    finally:
+        P.crystal_finalize()
+    return out("overhead", {"rows": rows, "reps": reps,
+                            "note": "job layer: pooled buffers, one compute stream, "
+                                    "one job in flight"})
+
+
+# --------------------------------------------------------------- naive stages
+
+def naive_stages(P, torch, gen, sizes=(64 << 10, 1 << 20, 8 << 20, 64 << 20), reps=5):
+    """Stage breakdown of the naive per-job direct-hashing path (the paper's
+    Fig. 6): allocation, copy in, kernels, copy out, free."""
+    rows = []
+    direct = P.crystal_direct_params(segment_bytes=4096)
+    for n in sizes:
+        host = torch.from_numpy(gen.random_bytes(n + 5, n)).pin_memory()
+        cap = P.crystal_output_bytes(P.K_MD5_DIRECT, n, direct)
+        o = np.zeros(cap, np.uint8)
+        acc = {k: [] for k in ("alloc_ms", "copy_in_ms", "kernel_ms", "copy_out_ms",
+                               "free_ms", "total_ms")}
+        for r in range(reps + 1):
+            _, st = P.crystal_naive_run(P.K_MD5_DIRECT, direct, host.data_ptr(), n, o, cap)
+            if r >= 1:
+                for k in acc:
+                    acc[k].append(getattr(st, k))
+        row = {"bytes": n, **{k: round(statistics.mean(v), 4) for k, v in acc.items()}}
+        row["alloc_share"] = round(row["alloc_ms"] / row["total_ms"], 3)
+        rows.append(row)
+    return out("naive_stages", {"rows": rows})
+
+
+# ----------------------------------------------------------------- stream_len
+
+def stream_len(P, torch, gen, lengths=(1, 2, 4, 8, 16, 32, 64)):
+    """A stream of L jobs of 1 MiB direct hashing (the paper's Fig. 8): all L
+    submitted at once through the job layer (pooled buffers, copy/compute
+    overlap, batching) vs the naive path run L times; wall time per stream."""
+    n = 1 << 20
+    direct = P.crystal_direct_params(segment_bytes=4096)
+    cap = P.crystal_output_bytes(P.K_MD5_DIRECT, n, direct)
+    L_max = max(lengths)
+    host = torch.empty(L_max * n, dtype=torch.uint8).pin_memory()
+    gen.fill(gen.sub_seed(gen.config_seed(1), 9), host.data_ptr(), L_max * n)
+    outs = torch.empty((L_max, cap), dtype=torch.uint8).pin_memory()
+    rows = []
+    P.crystal_init(max_input_bytes=n, host_pool_bytes=16 << 20, device_pool_bytes=1 << 30,
+                   n_streams=3, max_in_flight=64)
+    try:
+        for L in lengths:
+            jobs = (P.crystal_drive_job * L)()
+            for k in range(L):
+                jobs[k].h_in = host.data_ptr() + k * n
+                jobs[k].bytes = n
+                jobs[k].h_out = outs.data_ptr() + k * cap
+                jobs[k].out_cap = cap
+                jobs[k].kernel_id = P.K_MD5_DIRECT
+            P.crystal_drive(jobs, direct, None, window=0)  # warm
+            walls = []
+            for r in range(10):
+                res = P.crystal_drive(jobs, direct, None, window=0)
+                assert res.ok == L
+                walls.append(res.wall_s * 1e3)
+            o = np.zeros(cap, np.uint8)
+            t0 = time.perf_counter()
+            for k in range(L):
+                P.crystal_naive_run(P.K_MD5_DIRECT, direct, host.data_ptr() + k * n, n, o, cap)
+            naive_ms = (time.perf_counter() - t0) * 1e3
+            jm = statistics.median(walls)
+            rows.append({"jobs": L, "pipelined_ms": round(jm, 3), "naive_ms": round(naive_ms, 3),
+                         "speedup": round(naive_ms / jm, 2),
+                         "pipelined_gbps": round(L * n / 1e9 / (jm / 1e3), 2)})
+    finally:
+        P.crystal_finalize()
+    return out("stream_len", {"job_bytes": n, "rows": rows})
 
 
 # -------------------------------------------------------------------- chunking
@@ -344,7 +477,9 @@ def batch(P, torch, gen, n_buf, reps=20, sample_single=20000):
 
 def main() -> int:
     ap = argparse.ArgumentParser(description="per-workload measurements")
-    ap.add_argument("--only", default="", help="comma list: direct_one,chunking,serving,batch")
+    ap.add_argument("--only", default="",
+                    help="comma list: direct_one,overhead,naive_stages,stream_len,chunking,"
+                         "serving,batch")
     ap.add_argument("--quick", action="store_true", help="fewer jobs / buffers")
     ap.add_argument("--loads", default="5,10,20,30,40,45,50")
     ap.add_argument("--serving-jobs", type=int, default=0)
@@ -361,6 +496,12 @@ def main() -> int:
     want = lambda n: not only or n in only
     if want("direct_one"):
         direct_one(P, torch, gen)
+    if want("overhead"):
+        overhead(P, torch, gen)
+    if want("naive_stages"):
+        naive_stages(P, torch, gen)
+    if want("stream_len"):
+        stream_len(P, torch, gen)
     if want("chunking"):
         chunking(P, torch, gen)
     if want("batch"):

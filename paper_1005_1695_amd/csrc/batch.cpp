@@ -334,7 +334,7 @@ int crystal_batch_plan(const crystal_batch_desc *d, int tune_flags,
         return fail(CRYSTAL_EINVAL, "bad tuning: block %% 64, <= 1024; streams <= 8");
     }
     if (tune_flags == CRYSTAL_TUNE_FULL) {
-        for (uint32_t sorted : {4096u, 65536u, 1u, 0u})
+        for (uint32_t sorted : {256u, 1024u, 4096u, 65536u, 1u, 0u})
             for (uint32_t S : {1u, 2u})
                 for (uint32_t blk : {64u, 256u})
                     for (uint32_t wps : {2u, 4u, 8u})
