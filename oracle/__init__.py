@@ -4,7 +4,7 @@ Thin ctypes wrapper over ``oracle.c`` (plain single-threaded C).  Only the
 test suite, ``__graft_entry__.smoke()`` and the benchmark's ``cpu_baseline``
 leg may import this package; the GPU library never does, and the two share no
 code.  Definitions and their sources are listed in the header of ``oracle.c``
-(RFC 1321 for MD5; the paper's direct-hashing and content-addressable
+(RFC 1321 for MD5, FIPS 180-4 for SHA-1; the paper's direct-hashing and content-addressable
 chunking primitives, Sec. 2.2 and Sec. 5.2).
 """
 from __future__ import annotations
@@ -48,6 +48,8 @@ def _L():
         vp, sz, u64, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int
         sigs = {
             "oracle_md5": ([vp, sz, vp], None),
+            "oracle_sha1": ([vp, sz, vp], None),
+            "oracle_sha1_direct": ([vp, sz, sz, vp, vp], sz),
             "oracle_direct": ([vp, sz, sz, vp, vp], sz),
             "oracle_md5_batch": ([vp, vp, vp, sz, vp], None),
             "oracle_md5_chunks": ([vp, vp, sz, vp], None),
@@ -92,6 +94,24 @@ def direct(data, segment: int = DEFAULT_SEGMENT):
     seg = np.zeros((max(nseg, 1), 16), dtype=np.uint8)
     root = np.zeros(16, dtype=np.uint8)
     got = _L().oracle_direct(_p(buf), buf.size, segment, _p(seg), _p(root))
+    assert got == nseg
+    return seg[:nseg], root.tobytes()
+
+
+def sha1(data) -> bytes:
+    buf = _u8(data)
+    out = np.zeros(20, dtype=np.uint8)
+    _L().oracle_sha1(_p(buf), buf.size, _p(out))
+    return out.tobytes()
+
+
+def sha1_direct(data, segment: int = DEFAULT_SEGMENT):
+    """(segment SHA-1 digests as uint8[n_seg, 20], root digest bytes)."""
+    buf = _u8(data)
+    nseg = (buf.size + segment - 1) // segment
+    seg = np.zeros((max(nseg, 1), 20), dtype=np.uint8)
+    root = np.zeros(20, dtype=np.uint8)
+    got = _L().oracle_sha1_direct(_p(buf), buf.size, segment, _p(seg), _p(root))
     assert got == nseg
     return seg[:nseg], root.tobytes()
 

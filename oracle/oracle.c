@@ -8,7 +8,11 @@
  *
  * What it computes and where each definition comes from:
  *   - MD5: RFC 1321, Sec. 3.1-3.5 (padding, length, buffer init, the four
- *     rounds, output).  The paper's application is StoreGPU's hashing of a
+ *     rounds, output).
+ *   - SHA-1: FIPS 180-4, Sec. 4.1.1, 4.2.1, 5.1.1, 5.3.1, 6.1.2; direct
+ *     hashing with SHA-1 (20-byte segment digests, root over their
+ *     concatenation) is the variant of the paper's own measurements
+ *     (Sec. 5.2).  The paper's application is StoreGPU's hashing of a
  *     stream of data blocks (Sec. 2.2, Sec. 5.2); it measures SHA1 there, and
  *     this build fixes MD5 as the digest.
  *   - Direct hashing: the "direct hashing" primitive of Sec. 5.2 (Fig. 6):
@@ -25,7 +29,7 @@
  *     when s < N.  The window is never reset at chunk boundaries.
  *
  * Parity status: every function here is pinned by the CPU test suite
- * (hashlib/OpenSSL and md5sum for MD5, brute-force polynomial sums for the
+ * (hashlib/OpenSSL and md5sum for MD5, hashlib and sha1sum for SHA-1, brute-force polynomial sums for the
  * window hash, the closed-form all-zero and no-hit cases, chunk-rule
  * invariants, brute-force enumeration of the rule, split invariance).
  */
@@ -180,6 +184,99 @@ void oracle_md5_chunks(const uint8_t *buf, const uint64_t *ends, size_t nch,
         oracle_md5(buf + lo, ends[k] - lo, out + 16 * k);
         lo = ends[k];
     }
+}
+
+/* ----------------------------------------------------------------- SHA-1 --- */
+/* FIPS 180-4: Sec. 5.1.1 (padding), 5.3.1 (initial hash value), 4.1.1 (the
+ * functions f_t), 4.2.1 (constants K_t), 6.1.2 (the computation: message
+ * schedule, working variables, intermediate hash update).  Words are
+ * big-endian; the 64-bit message length in bits ends the padded message. */
+
+static uint32_t osha1_f(int t, uint32_t x, uint32_t y, uint32_t z)
+{
+    if (t < 20)
+        return (x & y) ^ (~x & z);           /* Ch */
+    if (t < 40)
+        return x ^ y ^ z;                    /* Parity */
+    if (t < 60)
+        return (x & y) ^ (x & z) ^ (y & z);  /* Maj */
+    return x ^ y ^ z;                        /* Parity */
+}
+
+static uint32_t osha1_k(int t)
+{
+    if (t < 20)
+        return 0x5a827999u;
+    if (t < 40)
+        return 0x6ed9eba1u;
+    if (t < 60)
+        return 0x8f1bbcdcu;
+    return 0xca62c1d6u;
+}
+
+static void osha1_block(uint32_t H[5], const uint8_t blk[64])
+{
+    uint32_t W[80];
+    for (int t = 0; t < 16; t++)
+        W[t] = ((uint32_t)blk[4 * t] << 24) | ((uint32_t)blk[4 * t + 1] << 16) |
+               ((uint32_t)blk[4 * t + 2] << 8) | (uint32_t)blk[4 * t + 3];
+    for (int t = 16; t < 80; t++)
+        W[t] = rotl32(W[t - 3] ^ W[t - 8] ^ W[t - 14] ^ W[t - 16], 1);
+    uint32_t a = H[0], b = H[1], c = H[2], d = H[3], e = H[4];
+    for (int t = 0; t < 80; t++) {
+        uint32_t T = rotl32(a, 5) + osha1_f(t, b, c, d) + e + osha1_k(t) + W[t];
+        e = d;
+        d = c;
+        c = rotl32(b, 30);
+        b = a;
+        a = T;
+    }
+    H[0] += a;
+    H[1] += b;
+    H[2] += c;
+    H[3] += d;
+    H[4] += e;
+}
+
+void oracle_sha1(const uint8_t *p, size_t n, uint8_t out[20])
+{
+    uint32_t H[5] = {0x67452301u, 0xefcdab89u, 0x98badcfeu, 0x10325476u, 0xc3d2e1f0u};
+    size_t i = 0;
+    for (; i + 64 <= n; i += 64)
+        osha1_block(H, p + i);
+    /* padding: the remaining bytes, 0x80, zeros, 64-bit big-endian bit count */
+    uint8_t last[128];
+    size_t r = n - i;
+    memset(last, 0, sizeof last);
+    memcpy(last, p + i, r);
+    last[r] = 0x80;
+    size_t total = r + 1 + 8 <= 64 ? 64 : 128;
+    uint64_t bits = (uint64_t)n * 8;
+    for (int k = 0; k < 8; k++)
+        last[total - 1 - k] = (uint8_t)(bits >> (8 * k));
+    for (size_t off = 0; off < total; off += 64)
+        osha1_block(H, last + off);
+    for (int k = 0; k < 5; k++) {
+        out[4 * k] = (uint8_t)(H[k] >> 24);
+        out[4 * k + 1] = (uint8_t)(H[k] >> 16);
+        out[4 * k + 2] = (uint8_t)(H[k] >> 8);
+        out[4 * k + 3] = (uint8_t)H[k];
+    }
+}
+
+/* Direct hashing with SHA-1 (the digest the paper's application measures):
+ * SHA-1 of every `seg`-byte segment, then SHA-1 of the concatenated 20-byte
+ * segment digests.  Returns the segment count. */
+size_t oracle_sha1_direct(const uint8_t *buf, size_t n, size_t seg,
+                          uint8_t *seg_digests, uint8_t root[20])
+{
+    size_t nseg = (n + seg - 1) / seg;
+    for (size_t j = 0; j < nseg; j++) {
+        size_t lo = j * seg, hi = lo + seg < n ? lo + seg : n;
+        oracle_sha1(buf + lo, hi - lo, seg_digests + 20 * j);
+    }
+    oracle_sha1(seg_digests, 20 * nseg, root);
+    return nseg;
 }
 
 /* ------------------------------------------------------------ window hash --- */

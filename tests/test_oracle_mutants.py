@@ -39,6 +39,18 @@ MUTANTS = {
     "direct_root_over_data": ("oracle_md5(seg_digests, 16 * nseg, root);",
                               "oracle_md5(buf, n, root);"),
     "candidate_early": ("if (i + 1 >= OW && (w & m) == 0) {", "if ((w & m) == 0) {"),
+    "sha1_schedule_rot": ("W[t] = rotl32(W[t - 3] ^ W[t - 8] ^ W[t - 14] ^ W[t - 16], 1);",
+                          "W[t] = W[t - 3] ^ W[t - 8] ^ W[t - 14] ^ W[t - 16];"),
+    "sha1_maj": ("return (x & y) ^ (x & z) ^ (y & z);  /* Maj */",
+                 "return (x & y) ^ (x & z);  /* Maj */"),
+    "sha1_k3": ("return 0x8f1bbcdcu;", "return 0x8f1bbcdbu;"),
+    "sha1_rot30": ("c = rotl32(b, 30);", "c = rotl32(b, 2);"),
+    "sha1_little_endian_len": ("last[total - 1 - k] = (uint8_t)(bits >> (8 * k));",
+                               "last[total - 8 + k] = (uint8_t)(bits >> (8 * k));"),
+    "sha1_pad_boundary": ("size_t total = r + 1 + 8 <= 64 ? 64 : 128;",
+                          "size_t total = r + 8 <= 64 ? 64 : 128;"),
+    "sha1_direct_root_width": ("oracle_sha1(seg_digests, 20 * nseg, root);",
+                               "oracle_sha1(seg_digests, 16 * nseg, root);"),
 }
 
 
@@ -99,6 +111,13 @@ def _pins_pass():
         if bytes(dg[k]) != h(mid[lo:int(x)]):
             return False
         lo = int(x)
+    h1 = lambda b: hashlib.sha1(bytes(b)).digest()
+    for n in (0, 3, 55, 56, 64, 100, 1000, 5000):
+        if oracle.sha1(data[:n]) != h1(data[:n]):
+            return False
+    seg1, root1 = oracle.sha1_direct(d9)
+    if root1 != h1(b"".join(h1(p) for p in pieces)):
+        return False
     return True
 
 
