@@ -66,6 +66,8 @@ extern "C" {
 #define CRYSTAL_K_MD5_DIRECT 1 /* direct block hashing */
 #define CRYSTAL_K_CDC 2        /* content-defined chunking + per-chunk MD5 */
 #define CRYSTAL_K_MD5 3        /* one MD5 of the whole input */
+#define CRYSTAL_K_SHA1_DIRECT 4 /* direct block hashing with SHA-1 (FIPS 180-4), the
+                                   digest of the paper's measurements (Sec. 5.2) */
 
 /* Direct hashing parameters.  segment_bytes: multiple of 64, 0 = 4096. */
 typedef struct crystal_direct_params {
@@ -175,6 +177,8 @@ size_t crystal_buffer_size(const crystal_buf *b);
  * crystal_output_bytes(kernel_id, in_bytes, params).
  * Output layouts:
  *   MD5_DIRECT: n_seg digests (16 B each) then the root digest (16 B)
+ *   SHA1_DIRECT: n_seg digests (20 B each) then the root digest (20 B);
+ *               the root is SHA-1 of the concatenated segment digests
  *   CDC:        uint64 n_chunks, uint64 ends[n_chunks] (exclusive end
  *               offsets, last = in_bytes), then n_chunks 16-byte digests
  *   MD5:        one 16-byte digest
@@ -232,6 +236,28 @@ int crystal_md5_segments_device(const void *d_in, const uint64_t *d_job_off,
 int crystal_md5_roots_device(const uint64_t *d_seg_base, uint32_t n_jobs,
                              uint32_t segment_bytes, const void *d_seg_digests,
                              void *d_roots, void *stream);
+
+/* Direct hashing with SHA-1 (FIPS 180-4; the digest of the paper's own
+ * direct-hashing measurements, Sec. 5.2): same arguments and job layout as
+ * crystal_md5_direct_device, with 20-byte digests -- d_seg_digests holds
+ * n_segments x 20 B (job j's at byte 20 * d_seg_base[j]), d_roots n_jobs x
+ * 20 B, and each root is SHA-1 over the job's concatenated segment digests.
+ * The digest array must be readable up to the next 16-byte boundary after
+ * its last byte (the root loader reads whole 16-byte vectors).  The two
+ * steps are callable on their own, as for MD5. */
+int crystal_sha1_direct_device(const void *d_in, const uint64_t *d_job_off,
+                               const uint64_t *d_job_len,
+                               const uint64_t *d_seg_base, uint32_t n_jobs,
+                               uint64_t n_segments, uint32_t segment_bytes,
+                               void *d_seg_digests, void *d_roots, void *stream);
+int crystal_sha1_segments_device(const void *d_in, const uint64_t *d_job_off,
+                                 const uint64_t *d_job_len,
+                                 const uint64_t *d_seg_base, uint32_t n_jobs,
+                                 uint64_t n_segments, uint32_t segment_bytes,
+                                 void *d_seg_digests, void *stream);
+int crystal_sha1_roots_device(const uint64_t *d_seg_base, uint32_t n_jobs,
+                              uint32_t segment_bytes, const void *d_seg_digests,
+                              void *d_roots, void *stream);
 
 /* MD5 of n_buf buffers: buffer m is d_arena[d_off[m], d_off[m] + d_len[m]),
  * digest to d_out + 16 m.  d_order (optional, n_buf entries) is the order in

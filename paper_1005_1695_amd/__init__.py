@@ -13,7 +13,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (CALLBACK, CrystalError, K_CDC, K_MD5, K_MD5_DIRECT, K_NOP,
+from ._lib import (CALLBACK, CrystalError, K_CDC, K_MD5, K_MD5_DIRECT, K_NOP, K_SHA1_DIRECT,
                    NONBLOCK, PENDING, check, crystal_batch_desc,
                    crystal_batch_tuning, crystal_cdc_params, crystal_config,
                    crystal_direct_params, crystal_drive_job,
@@ -76,6 +76,30 @@ def crystal_md5_roots_device(d_seg_base, n_jobs, segment_bytes, d_seg_digests,
     return check(load().crystal_md5_roots_device(
         _ptr(d_seg_base), n_jobs, segment_bytes, _ptr(d_seg_digests), _ptr(d_roots),
         _stream(stream)), "crystal_md5_roots_device")
+
+
+def crystal_sha1_direct_device(d_in, d_job_off, d_job_len, d_seg_base, n_jobs,
+                               n_segments, segment_bytes, d_seg_digests, d_roots,
+                               stream=None):
+    return check(load().crystal_sha1_direct_device(
+        _ptr(d_in), _ptr(d_job_off), _ptr(d_job_len), _ptr(d_seg_base), n_jobs,
+        n_segments, segment_bytes, _ptr(d_seg_digests), _ptr(d_roots),
+        _stream(stream)), "crystal_sha1_direct_device")
+
+
+def crystal_sha1_segments_device(d_in, d_job_off, d_job_len, d_seg_base, n_jobs,
+                                 n_segments, segment_bytes, d_seg_digests, stream=None):
+    return check(load().crystal_sha1_segments_device(
+        _ptr(d_in), _ptr(d_job_off), _ptr(d_job_len), _ptr(d_seg_base), n_jobs,
+        n_segments, segment_bytes, _ptr(d_seg_digests), _stream(stream)),
+        "crystal_sha1_segments_device")
+
+
+def crystal_sha1_roots_device(d_seg_base, n_jobs, segment_bytes, d_seg_digests,
+                              d_roots, stream=None):
+    return check(load().crystal_sha1_roots_device(
+        _ptr(d_seg_base), n_jobs, segment_bytes, _ptr(d_seg_digests), _ptr(d_roots),
+        _stream(stream)), "crystal_sha1_roots_device")
 
 
 def crystal_md5_batch_device(d_arena, d_off, d_len, d_order, n_buf, d_out,
@@ -149,13 +173,16 @@ def seg_table(job_lengths, segment: int = DEFAULT_SEGMENT):
 
 
 def direct_device(d_in, job_offsets, job_lengths, segment: int = DEFAULT_SEGMENT,
-                  stream=None):
-    """Direct hashing of several jobs already resident in d_in.
+                  stream=None, hash: str = "md5"):
+    """Direct hashing of several jobs already resident in d_in, with MD5
+    (hash="md5", 16-byte digests) or SHA-1 (hash="sha1", 20-byte digests).
 
-    Returns (segment digests [S,16], roots [J,16], seg_base) as device tensors
+    Returns (segment digests [S,D], roots [J,D], seg_base) as device tensors
     (seg_base as numpy)."""
     import torch
     dev = d_in.device
+    width, fn = ((16, crystal_md5_direct_device) if hash == "md5" else
+                 (20, crystal_sha1_direct_device))
     off = np.asarray(job_offsets, dtype=np.uint64)
     ln = np.asarray(job_lengths, dtype=np.uint64)
     base = seg_table(ln, segment)
@@ -163,10 +190,12 @@ def direct_device(d_in, job_offsets, job_lengths, segment: int = DEFAULT_SEGMENT
     t_off = torch.from_numpy(off.view(np.int64)).to(dev)
     t_len = torch.from_numpy(ln.view(np.int64)).to(dev)
     t_base = torch.from_numpy(base.view(np.int64)).to(dev)
-    seg = torch.empty((max(S, 1), 16), dtype=torch.uint8, device=dev)
-    roots = torch.empty((max(len(off), 1), 16), dtype=torch.uint8, device=dev)
-    crystal_md5_direct_device(d_in, t_off, t_len, t_base, len(off), S, segment,
-                              seg, roots, stream)
+    # digest array padded to a multiple of 16 bytes (the root loader reads
+    # whole 16-byte vectors)
+    flat = torch.empty(((max(S, 1) * width + 15) // 16) * 16, dtype=torch.uint8, device=dev)
+    seg = flat[:max(S, 1) * width].view(max(S, 1), width)
+    roots = torch.empty((max(len(off), 1), width), dtype=torch.uint8, device=dev)
+    fn(d_in, t_off, t_len, t_base, len(off), S, segment, seg, roots, stream)
     return seg[:S], roots[:len(off)], base, (t_off, t_len, t_base)
 
 

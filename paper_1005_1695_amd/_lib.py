@@ -22,7 +22,7 @@ c_int = ctypes.c_int
 OK = 0
 EINVAL, EAGAIN, ENOMEM, EBUSY, ETIMEDOUT, EDEVICE, ESTATE, ECANCELED = range(-1, -9, -1)
 PENDING = 1
-K_NOP, K_MD5_DIRECT, K_CDC, K_MD5 = 0, 1, 2, 3
+K_NOP, K_MD5_DIRECT, K_CDC, K_MD5, K_SHA1_DIRECT = 0, 1, 2, 3, 4
 NONBLOCK = 1
 TUNE_NONE, TUNE_FULL = 0, 1
 
@@ -114,6 +114,11 @@ SIGNATURES = {
     "crystal_md5_segments_device": ([c_vp, c_vp, c_vp, c_vp, c_u32, c_u64, c_u32, c_vp,
                                      c_vp], c_int),
     "crystal_md5_roots_device": ([c_vp, c_u32, c_u32, c_vp, c_vp, c_vp], c_int),
+    "crystal_sha1_direct_device": ([c_vp, c_vp, c_vp, c_vp, c_u32, c_u64, c_u32, c_vp,
+                                    c_vp, c_vp], c_int),
+    "crystal_sha1_segments_device": ([c_vp, c_vp, c_vp, c_vp, c_u32, c_u64, c_u32, c_vp,
+                                      c_vp], c_int),
+    "crystal_sha1_roots_device": ([c_vp, c_u32, c_u32, c_vp, c_vp, c_vp], c_int),
     "crystal_md5_batch_device": ([c_vp, c_vp, c_vp, c_vp, c_u64, c_vp, c_u32, c_u32,
                                   c_vp], c_int),
     "crystal_cdc_workspace_bytes": ([c_u64, P(crystal_cdc_params)], c_sz),

@@ -143,37 +143,16 @@ extern "C" {
 
 const char *crystal_last_error(void) { return g_err; }
 
-int crystal_md5_direct_device(const void *d_in, const uint64_t *d_job_off,
-                              const uint64_t *d_job_len, const uint64_t *d_seg_base,
-                              uint32_t n_jobs, uint64_t n_segments, uint32_t segment_bytes,
-                              void *d_seg_digests, void *d_roots, void *stream)
-{
-    if (segment_bytes == 0)
-        segment_bytes = 4096;
-    if (segment_bytes % 64 || segment_bytes > (1u << 30))
-        return fail(CRYSTAL_EINVAL, "segment_bytes must be a multiple of 64 and <= 2^30");
-    if (n_jobs == 0)
-        return CRYSTAL_OK;
-    if (!d_job_off || !d_job_len || !d_seg_base || !d_roots ||
-        (n_segments && (!d_in || !d_seg_digests)))
-        return fail(CRYSTAL_EINVAL, "null pointer argument");
-    JobTable jt{d_job_off, d_job_len, d_seg_base, n_jobs, 0};
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_md5_segments((const uint8_t *)d_in, jt, segment_bytes, n_segments,
-                                       (uint8_t *)d_seg_digests, s);
-    if (e != hipSuccess)
-        return hip_fail(e, "md5_segments launch");
-    e = launch_md5_roots((const uint8_t *)d_seg_digests, jt, segment_bytes,
-                         (uint8_t *)d_roots, s);
-    if (e != hipSuccess)
-        return hip_fail(e, "md5_roots launch");
-    return CRYSTAL_OK;
-}
+} // extern "C"
 
-int crystal_md5_segments_device(const void *d_in, const uint64_t *d_job_off,
-                                const uint64_t *d_job_len, const uint64_t *d_seg_base,
-                                uint32_t n_jobs, uint64_t n_segments, uint32_t segment_bytes,
-                                void *d_seg_digests, void *stream)
+// Direct hashing with MD5 (16-byte digests) or SHA-1 (20-byte digests):
+// validation and launches shared by the device-level entry points.
+enum class DirectHash { Md5, Sha1 };
+
+static int direct_segments(DirectHash h, const void *d_in, const uint64_t *d_job_off,
+                           const uint64_t *d_job_len, const uint64_t *d_seg_base,
+                           uint32_t n_jobs, uint64_t n_segments, uint32_t segment_bytes,
+                           void *d_seg_digests, void *stream)
 {
     if (segment_bytes == 0)
         segment_bytes = 4096;
@@ -184,16 +163,21 @@ int crystal_md5_segments_device(const void *d_in, const uint64_t *d_job_off,
     if (!d_in || !d_job_off || !d_job_len || !d_seg_base || !d_seg_digests)
         return fail(CRYSTAL_EINVAL, "null pointer argument");
     JobTable jt{d_job_off, d_job_len, d_seg_base, n_jobs, 0};
-    hipError_t e = launch_md5_segments((const uint8_t *)d_in, jt, segment_bytes, n_segments,
-                                       (uint8_t *)d_seg_digests, (hipStream_t)stream);
+    hipError_t e = h == DirectHash::Md5
+                       ? launch_md5_segments((const uint8_t *)d_in, jt, segment_bytes,
+                                             n_segments, (uint8_t *)d_seg_digests,
+                                             (hipStream_t)stream)
+                       : launch_sha1_segments((const uint8_t *)d_in, jt, segment_bytes,
+                                              n_segments, (uint8_t *)d_seg_digests,
+                                              (hipStream_t)stream);
     if (e != hipSuccess)
-        return hip_fail(e, "md5_segments launch");
+        return hip_fail(e, "segments launch");
     return CRYSTAL_OK;
 }
 
-int crystal_md5_roots_device(const uint64_t *d_seg_base, uint32_t n_jobs,
-                             uint32_t segment_bytes, const void *d_seg_digests, void *d_roots,
-                             void *stream)
+static int direct_roots(DirectHash h, const uint64_t *d_seg_base, uint32_t n_jobs,
+                        uint32_t segment_bytes, const void *d_seg_digests, void *d_roots,
+                        void *stream)
 {
     if (segment_bytes == 0)
         segment_bytes = 4096;
@@ -204,11 +188,87 @@ int crystal_md5_roots_device(const uint64_t *d_seg_base, uint32_t n_jobs,
     if (!d_seg_base || !d_roots)
         return fail(CRYSTAL_EINVAL, "null pointer argument");
     JobTable jt{nullptr, nullptr, d_seg_base, n_jobs, 0};
-    hipError_t e = launch_md5_roots((const uint8_t *)d_seg_digests, jt, segment_bytes,
-                                    (uint8_t *)d_roots, (hipStream_t)stream);
+    hipError_t e = h == DirectHash::Md5
+                       ? launch_md5_roots((const uint8_t *)d_seg_digests, jt, segment_bytes,
+                                          (uint8_t *)d_roots, (hipStream_t)stream)
+                       : launch_sha1_roots((const uint8_t *)d_seg_digests, jt, segment_bytes,
+                                           (uint8_t *)d_roots, (hipStream_t)stream);
     if (e != hipSuccess)
-        return hip_fail(e, "md5_roots launch");
+        return hip_fail(e, "roots launch");
     return CRYSTAL_OK;
+}
+
+static int direct_both(DirectHash h, const void *d_in, const uint64_t *d_job_off,
+                       const uint64_t *d_job_len, const uint64_t *d_seg_base, uint32_t n_jobs,
+                       uint64_t n_segments, uint32_t segment_bytes, void *d_seg_digests,
+                       void *d_roots, void *stream)
+{
+    if (segment_bytes % 64 || segment_bytes > (1u << 30))
+        return fail(CRYSTAL_EINVAL, "segment_bytes must be a multiple of 64 and <= 2^30");
+    if (n_jobs == 0)
+        return CRYSTAL_OK;
+    if (!d_job_off || !d_job_len || !d_seg_base || !d_roots ||
+        (n_segments && (!d_in || !d_seg_digests)))
+        return fail(CRYSTAL_EINVAL, "null pointer argument");
+    int rc = direct_segments(h, d_in, d_job_off, d_job_len, d_seg_base, n_jobs, n_segments,
+                             segment_bytes, d_seg_digests, stream);
+    if (rc)
+        return rc;
+    return direct_roots(h, d_seg_base, n_jobs, segment_bytes, d_seg_digests, d_roots, stream);
+}
+
+extern "C" {
+
+int crystal_md5_direct_device(const void *d_in, const uint64_t *d_job_off,
+                              const uint64_t *d_job_len, const uint64_t *d_seg_base,
+                              uint32_t n_jobs, uint64_t n_segments, uint32_t segment_bytes,
+                              void *d_seg_digests, void *d_roots, void *stream)
+{
+    return direct_both(DirectHash::Md5, d_in, d_job_off, d_job_len, d_seg_base, n_jobs,
+                       n_segments, segment_bytes, d_seg_digests, d_roots, stream);
+}
+
+int crystal_md5_segments_device(const void *d_in, const uint64_t *d_job_off,
+                                const uint64_t *d_job_len, const uint64_t *d_seg_base,
+                                uint32_t n_jobs, uint64_t n_segments, uint32_t segment_bytes,
+                                void *d_seg_digests, void *stream)
+{
+    return direct_segments(DirectHash::Md5, d_in, d_job_off, d_job_len, d_seg_base, n_jobs,
+                           n_segments, segment_bytes, d_seg_digests, stream);
+}
+
+int crystal_md5_roots_device(const uint64_t *d_seg_base, uint32_t n_jobs,
+                             uint32_t segment_bytes, const void *d_seg_digests, void *d_roots,
+                             void *stream)
+{
+    return direct_roots(DirectHash::Md5, d_seg_base, n_jobs, segment_bytes, d_seg_digests,
+                        d_roots, stream);
+}
+
+int crystal_sha1_direct_device(const void *d_in, const uint64_t *d_job_off,
+                               const uint64_t *d_job_len, const uint64_t *d_seg_base,
+                               uint32_t n_jobs, uint64_t n_segments, uint32_t segment_bytes,
+                               void *d_seg_digests, void *d_roots, void *stream)
+{
+    return direct_both(DirectHash::Sha1, d_in, d_job_off, d_job_len, d_seg_base, n_jobs,
+                       n_segments, segment_bytes, d_seg_digests, d_roots, stream);
+}
+
+int crystal_sha1_segments_device(const void *d_in, const uint64_t *d_job_off,
+                                 const uint64_t *d_job_len, const uint64_t *d_seg_base,
+                                 uint32_t n_jobs, uint64_t n_segments, uint32_t segment_bytes,
+                                 void *d_seg_digests, void *stream)
+{
+    return direct_segments(DirectHash::Sha1, d_in, d_job_off, d_job_len, d_seg_base, n_jobs,
+                           n_segments, segment_bytes, d_seg_digests, stream);
+}
+
+int crystal_sha1_roots_device(const uint64_t *d_seg_base, uint32_t n_jobs,
+                              uint32_t segment_bytes, const void *d_seg_digests, void *d_roots,
+                              void *stream)
+{
+    return direct_roots(DirectHash::Sha1, d_seg_base, n_jobs, segment_bytes, d_seg_digests,
+                        d_roots, stream);
 }
 
 int crystal_md5_batch_device(const void *d_arena, const uint64_t *d_off, const uint32_t *d_len,

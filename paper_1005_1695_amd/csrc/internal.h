@@ -31,6 +31,11 @@ hipError_t launch_md5_segments(const uint8_t *in, const JobTable &jt,
 hipError_t launch_md5_roots(const uint8_t *seg_digests, const JobTable &jt,
                             uint32_t seg_bytes, uint8_t *roots, hipStream_t s);
 hipError_t launch_md5_whole(const uint8_t *in, uint64_t n, uint8_t *out, hipStream_t s);
+// SHA-1 direct hashing (20-byte digests; same job-table conventions).
+hipError_t launch_sha1_segments(const uint8_t *in, const JobTable &jt, uint32_t seg_bytes,
+                                uint64_t n_segments, uint8_t *seg_digests, hipStream_t s);
+hipError_t launch_sha1_roots(const uint8_t *seg_digests, const JobTable &jt, uint32_t seg_bytes,
+                             uint8_t *roots, hipStream_t s);
 hipError_t launch_md5_batch(const uint8_t *arena, const uint64_t *off,
                             const uint32_t *len, const uint32_t *order,
                             uint64_t n, uint8_t *out, uint32_t block,

@@ -34,7 +34,8 @@ extern "C" int crystal_naive_run(int kernel_id, const void *params, const void *
             return fail(CRYSTAL_EINVAL, "chunking params: %s", why);
         g = cdc_geometry(n, cp);
         cap = cdc_max_chunks(n, cp);
-    } else if (kernel_id == CRYSTAL_K_MD5_DIRECT && params) {
+    } else if ((kernel_id == CRYSTAL_K_MD5_DIRECT || kernel_id == CRYSTAL_K_SHA1_DIRECT) &&
+               params) {
         const auto *dp = static_cast<const crystal_direct_params *>(params);
         if (dp->segment_bytes)
             seg = dp->segment_bytes;
@@ -65,6 +66,14 @@ extern "C" int crystal_naive_run(int kernel_id, const void *params, const void *
             e = launch_md5_segments(d_in, jt, seg, nseg, d_out, s);
             if (e == hipSuccess)
                 e = launch_md5_roots(d_out, jt, seg, d_out + 16 * nseg, s);
+            break;
+        }
+        case CRYSTAL_K_SHA1_DIRECT: {
+            JobTable jt{nullptr, nullptr, nullptr, 0, n};
+            const uint64_t nseg = (n + seg - 1) / seg;
+            e = launch_sha1_segments(d_in, jt, seg, nseg, d_out, s);
+            if (e == hipSuccess)
+                e = launch_sha1_roots(d_out, jt, seg, d_out + 20 * nseg, s);
             break;
         }
         case CRYSTAL_K_CDC: {

@@ -133,7 +133,9 @@ static bool plan_job(int kernel, size_t n, const void *params, Job *j, JobPlan *
         p->out_region = 256;
         p->d2h = 16;
         break;
-    case CRYSTAL_K_MD5_DIRECT: {
+    case CRYSTAL_K_MD5_DIRECT:
+    case CRYSTAL_K_SHA1_DIRECT: {
+        const size_t dlen = kernel == CRYSTAL_K_MD5_DIRECT ? 16 : 20;
         uint32_t seg = 4096;
         if (params) {
             const auto *dp = static_cast<const crystal_direct_params *>(params);
@@ -147,7 +149,7 @@ static bool plan_job(int kernel, size_t n, const void *params, Job *j, JobPlan *
         if (j)
             j->seg_bytes = seg;
         const uint64_t nseg = (n + seg - 1) / seg;
-        p->d2h = 16 * (nseg + 1);
+        p->d2h = dlen * (nseg + 1);
         p->out_region = al(p->d2h, 256);
         break;
     }
@@ -355,6 +357,14 @@ static hipError_t enqueue_batch(Lib *L, Batch *b)
             e = launch_md5_segments(d_in, jt, j->seg_bytes, nseg, d_out, st);
             if (e == hipSuccess)
                 e = launch_md5_roots(d_out, jt, j->seg_bytes, d_out + 16 * nseg, st);
+            break;
+        }
+        case CRYSTAL_K_SHA1_DIRECT: {
+            JobTable jt{nullptr, nullptr, nullptr, 0, j->n};
+            const uint64_t nseg = (j->n + j->seg_bytes - 1) / j->seg_bytes;
+            e = launch_sha1_segments(d_in, jt, j->seg_bytes, nseg, d_out, st);
+            if (e == hipSuccess)
+                e = launch_sha1_roots(d_out, jt, j->seg_bytes, d_out + 20 * nseg, st);
             break;
         }
         case CRYSTAL_K_CDC: {
@@ -570,7 +580,7 @@ int crystal_init(const crystal_config *cfg_in)
         cfg.max_in_flight = 4 * cfg.n_streams;
     // largest output and device need over all kernels for the largest input
     size_t max_out = 0, max_need = 0;
-    for (int k = 0; k <= CRYSTAL_K_MD5; k++) {
+    for (int k = 0; k <= CRYSTAL_K_SHA1_DIRECT; k++) {
         JobPlan p;
         const char *why;
         if (plan_job(k, cfg.max_input_bytes, nullptr, nullptr, &p, &why)) {

@@ -57,6 +57,10 @@ def test_output_sizes(P):
     assert P.crystal_output_bytes(99, 777, None) == 0
     bad = P.crystal_direct_params(segment_bytes=100)
     assert P.crystal_output_bytes(P.K_MD5_DIRECT, 1000, bad) == 0
+    assert P.crystal_output_bytes(P.K_SHA1_DIRECT, 1 << 20, dp) == 20 * 257
+    assert P.crystal_output_bytes(P.K_SHA1_DIRECT, 4097, dp) == 20 * 3
+    assert P.crystal_output_bytes(P.K_SHA1_DIRECT, 0, dp) == 20
+    assert P.crystal_output_bytes(P.K_SHA1_DIRECT, 1000, bad) == 0
 
 
 def test_cdc_sizes(P):
@@ -88,6 +92,10 @@ def test_device_calls_validate_before_launch(P):
     # segment size not a multiple of 64 -> EINVAL, no launch attempted
     rc = lib.crystal_md5_direct_device(1, 1, 1, 1, 1, 1, 100, 1, 1, None)
     assert rc == P._lib.EINVAL
+    rc = lib.crystal_sha1_direct_device(1, 1, 1, 1, 1, 1, 100, 1, 1, None)
+    assert rc == P._lib.EINVAL
+    rc = lib.crystal_sha1_roots_device(None, 3, 4096, 1, 1, None)
+    assert rc == P._lib.EINVAL
     rc = lib.crystal_md5_batch_device(1, 1, 1, None, 5, 1, 100, 0, None)
     assert rc == P._lib.EINVAL
     cp = P.cdc_params(3)
@@ -102,6 +110,8 @@ def test_device_calls_validate_before_launch(P):
     # zero-work calls succeed without launching anything
     assert lib.crystal_md5_direct_device(None, None, None, None, 0, 0, 0, None, None,
                                          None) == 0
+    assert lib.crystal_sha1_direct_device(None, None, None, None, 0, 0, 0, None, None,
+                                          None) == 0
     assert lib.crystal_md5_batch_device(None, None, None, None, 0, None, 0, 0, None) == 0
 
 

@@ -91,6 +91,66 @@ def test_direct_stream_full_size_sampled(P, torch_cuda):
         assert np.array_equal(_np(seg[int(base[j]):int(base[j + 1])]), es), j
 
 
+# ------------------------------------------------------- SHA-1 direct hashing
+
+def test_sha1_direct_one_job_1mib(P, torch_cuda):
+    data = gen.direct_one()
+    d, n = P.to_device_bytes(data)
+    seg, roots, base, _ = P.direct_device(d, [0], [n], hash="sha1")
+    exp_seg, exp_root = oracle.sha1_direct(data)
+    assert np.array_equal(_np(seg), exp_seg)
+    assert _np(roots)[0].tobytes() == exp_root
+
+
+def test_sha1_direct_ragged_jobs(P, torch_cuda):
+    """Ragged and empty jobs, two unaligned job starts, and (with 20-byte
+    digests) roots whose digest runs start only 4-byte aligned."""
+    lens = [0, 1, 15, 55, 56, 64, 4095, 4096, 4097, 8192 + 100, 100000, 3, 65536]
+    offs, o = [], 0
+    for i, ln in enumerate(lens):
+        o = (o + 15) // 16 * 16 + (7 if i in (2, 9) else 0)
+        offs.append(o)
+        o += ln
+    arena = gen.random_bytes(78, o + 64)
+    d, _ = P.to_device_bytes(arena)
+    seg, roots, base, _ = P.direct_device(d, offs, lens, hash="sha1")
+    seg, roots = _np(seg), _np(roots)
+    for j, (of, ln) in enumerate(zip(offs, lens)):
+        es, er = oracle.sha1_direct(arena[of:of + ln])
+        assert np.array_equal(seg[int(base[j]):int(base[j + 1])], es), j
+        assert roots[j].tobytes() == er, j
+
+
+@pytest.mark.parametrize("segment", [64, 192, 4096, 65536])
+def test_sha1_direct_segment_sizes(P, torch_cuda, segment):
+    data = gen.random_bytes(segment + 1, 300001)
+    d, n = P.to_device_bytes(data)
+    seg, roots, base, _ = P.direct_device(d, [0], [n], segment=segment, hash="sha1")
+    es, er = oracle.sha1_direct(data, segment)
+    assert np.array_equal(_np(seg), es)
+    assert _np(roots)[0].tobytes() == er
+
+
+def test_sha1_stream_full_size_sampled(P, torch_cuda):
+    """256 jobs x 8 MiB in one SHA-1 launch pair; a sample checked."""
+    torch = torch_cuda
+    n_jobs, job = 256, 8 << 20
+    seeds = gen.direct_stream_seeds(n_jobs)
+    host = torch.empty(n_jobs * job, dtype=torch.uint8).pin_memory()
+    gen.fill_multi(seeds, np.arange(n_jobs, dtype=np.uint64) * job,
+                   np.full(n_jobs, job, dtype=np.uint64), host.data_ptr())
+    d = host.to("cuda")
+    seg, roots, base, _ = P.direct_device(d, np.arange(n_jobs) * job, [job] * n_jobs,
+                                          hash="sha1")
+    torch.cuda.synchronize()
+    roots = _np(roots)
+    for j in (0, 3, 128, 255):
+        data = host[j * job:(j + 1) * job].numpy()
+        es, er = oracle.sha1_direct(data)
+        assert roots[j].tobytes() == er, j
+        assert np.array_equal(_np(seg[int(base[j]):int(base[j + 1])]), es), j
+
+
 # ------------------------------------------------------------------- batching
 
 def test_batch_small_vs_oracle(P, torch_cuda):

@@ -66,7 +66,8 @@ def test_direct_job_1mib_with_callback(lib):
 
 
 @pytest.mark.parametrize("kind", ["nop", "md5", "direct64", "cdc_small", "cdc_default",
-                                  "direct_ragged", "empty_cdc", "empty_direct"])
+                                  "direct_ragged", "empty_cdc", "empty_direct", "sha1",
+                                  "sha1_ragged", "empty_sha1"])
 def test_each_kernel_as_a_job(lib, kind):
     P = lib
     base = gen.cdc_base()
@@ -76,6 +77,13 @@ def test_each_kernel_as_a_job(lib, kind):
         k = P.K_NOP
     elif kind == "md5":
         k = P.K_MD5
+    elif kind.endswith("sha1") or kind.startswith("sha1"):
+        k = P.K_SHA1_DIRECT
+        params = P.crystal_direct_params(segment_bytes=4096)
+        if kind == "sha1_ragged":
+            data = data[:123457]
+        if kind == "empty_sha1":
+            data = data[:0]
     elif kind.startswith("direct"):
         k = P.K_MD5_DIRECT
         params = P.crystal_direct_params(segment_bytes=64 if kind == "direct64" else 4096)
@@ -101,6 +109,10 @@ def test_each_kernel_as_a_job(lib, kind):
         es, er = oracle.direct(data, seg)
         assert np.array_equal(out[:-16].reshape(-1, 16), es)
         assert out[-16:].tobytes() == er
+    elif k == P.K_SHA1_DIRECT:
+        es, er = oracle.sha1_direct(data, params.segment_bytes)
+        assert np.array_equal(out[:-20].reshape(-1, 20), es)
+        assert out[-20:].tobytes() == er
     else:
         ends, dig = P.parse_cdc_output(out)
         ee, ed = oracle.cdc(data, base, params.mask_bits, params.min_len, params.max_len)
@@ -296,6 +308,15 @@ def test_closed_loop_window(lib, torch_cuda):
     for k in range(n):
         _, er = oracle.direct(a[offs[k]:offs[k] + sizes[k]])
         assert outs[k].numpy()[-16:].tobytes() == er
+
+
+def test_naive_path_sha1(P, torch_cuda):
+    data = gen.random_bytes(31, 5 << 20 | 77)
+    out = np.zeros(P.crystal_output_bytes(P.K_SHA1_DIRECT, len(data), None), np.uint8)
+    ob, st = P.crystal_naive_run(P.K_SHA1_DIRECT, None, data, len(data), out, len(out))
+    es, er = oracle.sha1_direct(data)
+    assert ob == len(out) == 20 * (len(es) + 1)
+    assert np.array_equal(out[:-20].reshape(-1, 20), es) and out[-20:].tobytes() == er
 
 
 def test_naive_path_stage_times(P, torch_cuda):
