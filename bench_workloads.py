@@ -16,6 +16,8 @@ the streamed direct-hashing one).  Prints one JSON object per workload.
                (job layer vs naive path vs the copies alone).
   naive_stages stage breakdown of the naive direct-hashing path by size.
   stream_len   streams of 1..64 jobs of 1 MiB: job layer vs naive path.
+  sha1_stream  256 jobs x 8 MiB of direct hashing with SHA-1: device-resident
+               kernel times and ALU fraction; host-fed job layer vs naive.
   batch        1 000 000 buffers of 512 B..16 KiB resident on the device:
                tuned persistent plan (replay time, GB/s, integer-ALU and HBM
                fractions) vs one launch per buffer (timed on a sample).
@@ -267,6 +269,103 @@ def stream_len(P, torch, gen, lengths=(1, 2, 4, 8, 16, 32, 64)):
     return out("stream_len", {"job_bytes": n, "rows": rows})
 
 
+# ----------------------------------------------------------------- sha1_stream
+
+OPS_PER_SHA1_COMPRESSION = 80 * 5 + 64 * 3 + 5 + 16  # steps, schedule, state adds, byte swaps
+
+
+def sha1_stream(P, torch, gen, reps=10, n_streams=3, window=24):
+    """The streamed direct-hashing workload with SHA-1 (the digest the paper's
+    own measurements use): 256 jobs x 8 MiB.  Device-resident kernel times
+    (segments, roots, a serial step) with the segment kernel's integer-ALU
+    fraction; host-fed through the job layer (closed loop) vs the naive path."""
+    n_jobs, job = 256, 8 << 20
+    total = n_jobs * job
+    seeds = gen.direct_stream_seeds(n_jobs)
+    host = torch.empty(total, dtype=torch.uint8).pin_memory()
+    gen.fill_multi(seeds, np.arange(n_jobs, dtype=np.uint64) * np.uint64(job),
+                   np.full(n_jobs, job, dtype=np.uint64), host.data_ptr())
+    d = host.to("cuda")
+    lens = np.full(n_jobs, job, dtype=np.uint64)
+    base = P.seg_table(lens)
+    n_seg = int(base[-1])
+    t_off = torch.from_numpy((np.arange(n_jobs, dtype=np.uint64) * np.uint64(job))
+                             .view(np.int64)).cuda()
+    t_len = torch.from_numpy(lens.view(np.int64)).cuda()
+    t_base = torch.from_numpy(base.view(np.int64)).cuda()
+    seg = torch.empty((n_seg, 20), dtype=torch.uint8, device="cuda")
+    roots = torch.empty((n_jobs, 20), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    ts, tr, tt = [], [], []
+    for r in range(reps + 2):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(s)
+        P.crystal_sha1_segments_device(d, t_off, t_len, t_base, n_jobs, n_seg, 4096, seg,
+                                       s.cuda_stream)
+        e[1].record(s)
+        P.crystal_sha1_roots_device(t_base, n_jobs, 4096, seg, roots, s.cuda_stream)
+        e[2].record(s)
+        e[2].synchronize()
+        if r >= 2:
+            ts.append(e[0].elapsed_time(e[1]))
+            tr.append(e[1].elapsed_time(e[2]))
+            tt.append(e[0].elapsed_time(e[2]))
+    seg_ms, root_ms, step_ms = (statistics.mean(x) for x in (ts, tr, tt))
+    comps = n_seg * comp(4096)
+    alu = comps * OPS_PER_SHA1_COMPRESSION / (seg_ms / 1e3) / 1e12
+    dev_roots = roots.cpu().numpy()
+    # host-fed: job layer (closed loop, 12 jobs in the system) vs naive path
+    direct = P.crystal_direct_params(segment_bytes=4096)
+    cap = P.crystal_output_bytes(P.K_SHA1_DIRECT, job, direct)
+    outs = torch.empty((n_jobs, cap), dtype=torch.uint8).pin_memory()
+    P.crystal_init(max_input_bytes=job, host_pool_bytes=64 << 20, device_pool_bytes=1 << 30,
+                   n_streams=n_streams, max_in_flight=max(24, 2 * window))
+    try:
+        jobs = (P.crystal_drive_job * n_jobs)()
+        for j in range(n_jobs):
+            jobs[j].h_in = host.data_ptr() + j * job
+            jobs[j].bytes = job
+            jobs[j].h_out = outs.data_ptr() + j * cap
+            jobs[j].out_cap = cap
+            jobs[j].kernel_id = P.K_SHA1_DIRECT
+        P.crystal_drive(jobs, direct, None, window=window)
+        best = None
+        for _ in range(3):
+            res = P.crystal_drive(jobs, direct, None, window=window)
+            lat = [jobs[j].latency_s * 1e3 for j in range(n_jobs)]
+            g = res.bytes / 1e9 / res.wall_s
+            if best is None or g > best[0]:
+                best = (g, lat)
+        same = all(bytes(outs[j, cap - 20:].numpy()) == dev_roots[j].tobytes()
+                   for j in (0, 100, 255))
+    finally:
+        P.crystal_finalize()
+    o = np.zeros(cap, np.uint8)
+    t0 = time.perf_counter()
+    nl = []
+    for j in range(n_jobs):
+        _, st = P.crystal_naive_run(P.K_SHA1_DIRECT, direct, host.data_ptr() + j * job, job,
+                                    o, cap)
+        nl.append(st.total_ms)
+    naive = total / 1e9 / (time.perf_counter() - t0)
+    return out("sha1_stream", {
+        "jobs": n_jobs, "job_bytes": job,
+        "device_ms": {"segments": round(seg_ms, 4), "roots": round(root_ms, 4),
+                      "serial_step": round(step_ms, 4)},
+        "device_gbps_serial_step": round(total / 1e9 / (step_ms / 1e3), 1),
+        "segments_alu_tops": round(alu, 2), "segments_alu_frac": round(alu / INT32_PEAK_TOPS, 4),
+        "ops_per_compression": OPS_PER_SHA1_COMPRESSION,
+        "root_us_per_compression": round(root_ms * 1e3 / comp(20 * 2048), 3),
+        "pipelined_streams": n_streams, "pipelined_window": window,
+        "pipelined_gbps": round(best[0], 2), "pipelined_p50_ms": round(pct(best[1], 50), 3),
+        "pipelined_p99_ms": round(pct(best[1], 99), 3),
+        "naive_gbps": round(naive, 2), "naive_p50_ms": round(pct(nl, 50), 3),
+        "speedup_vs_naive": round(best[0] / naive, 2),
+        "link_frac": round(best[0] / LINK_PEAK_GBPS, 4),
+        "job_roots_match_device": bool(same),
+    })
+
+
 # -------------------------------------------------------------------- chunking
 
 def chunking(P, torch, gen, reps=10):
@@ -478,13 +577,15 @@ def batch(P, torch, gen, n_buf, reps=20, sample_single=20000):
 def main() -> int:
     ap = argparse.ArgumentParser(description="per-workload measurements")
     ap.add_argument("--only", default="",
-                    help="comma list: direct_one,overhead,naive_stages,stream_len,chunking,"
-                         "serving,batch")
+                    help="comma list: direct_one,overhead,naive_stages,stream_len,sha1_stream,"
+                         "chunking,serving,batch")
     ap.add_argument("--quick", action="store_true", help="fewer jobs / buffers")
     ap.add_argument("--loads", default="5,10,20,30,40,45,50")
     ap.add_argument("--serving-jobs", type=int, default=0)
     ap.add_argument("--serving-streams", type=int, default=3)
     ap.add_argument("--batch-buffers", type=int, default=0)
+    ap.add_argument("--sha1-streams", type=int, default=3)
+    ap.add_argument("--sha1-window", type=int, default=24)
     args = ap.parse_args()
     import torch
 
@@ -502,6 +603,8 @@ def main() -> int:
         naive_stages(P, torch, gen)
     if want("stream_len"):
         stream_len(P, torch, gen)
+    if want("sha1_stream"):
+        sha1_stream(P, torch, gen, n_streams=args.sha1_streams, window=args.sha1_window)
     if want("chunking"):
         chunking(P, torch, gen)
     if want("batch"):

@@ -191,11 +191,12 @@ struct Batch {
 };
 
 // Job-table slots: pinned host staging + device copy, one per batch in flight.
-// Arrays of kMaxBatch + 1 words: direct group off, len, seg_base, out_off;
-// chunking jobs in_off, out_off, ord_off, cap, lane0.
+// Arrays of kMaxBatch + 1 words: direct (MD5) group off, len, seg_base,
+// out_off; chunking jobs in_off, out_off, ord_off, cap, lane0; SHA-1 direct
+// group off, len, seg_base, out_off.
 constexpr uint32_t kMaxBatch = 32;
 constexpr size_t kTabN = kMaxBatch + 1;
-constexpr size_t kSlotWords = 9 * kTabN;
+constexpr size_t kSlotWords = 13 * kTabN;
 constexpr size_t kSlotBytes = 8 * kSlotWords;
 
 struct Lib {
@@ -279,19 +280,22 @@ static hipError_t enqueue_batch(Lib *L, Batch *b)
     }
     // grouped work needs a table slot: direct jobs with the first direct
     // job's segment size, and every chunking job
-    std::vector<Job *> group, cdc;
+    std::vector<Job *> group, cdc, sgroup;
     if (b->slot >= 0) {
         for (Job *j : b->jobs) {
             if (j->kernel == CRYSTAL_K_MD5_DIRECT &&
                 (group.empty() || j->seg_bytes == group[0]->seg_bytes))
                 group.push_back(j);
+            else if (j->kernel == CRYSTAL_K_SHA1_DIRECT &&
+                     (sgroup.empty() || j->seg_bytes == sgroup[0]->seg_bytes))
+                sgroup.push_back(j);
             else if (j->kernel == CRYSTAL_K_CDC)
                 cdc.push_back(j);
         }
     }
-    uint64_t total_seg = 0, chunk_lanes = 0;
+    uint64_t total_seg = 0, chunk_lanes = 0, sha_seg = 0;
     uint64_t *dtab = nullptr;
-    if ((!group.empty() || !cdc.empty()) && e == hipSuccess) {
+    if ((!group.empty() || !cdc.empty() || !sgroup.empty()) && e == hipSuccess) {
         uint64_t *h = L->table_host + (size_t)b->slot * kSlotWords;
         dtab = L->table_dev + (size_t)b->slot * kSlotWords;
         uint64_t *h_off = h, *h_len = h + kTabN, *h_base = h + 2 * kTabN,
@@ -321,6 +325,17 @@ static hipError_t enqueue_batch(Lib *L, Batch *b)
             chunk_lanes += al(j->cap, 64);
         }
         c_lane0[cdc.size()] = chunk_lanes;
+        uint64_t *s_off = h + 9 * kTabN, *s_len = h + 10 * kTabN, *s_base = h + 11 * kTabN,
+                 *s_out = h + 12 * kTabN;
+        for (size_t k = 0; k < sgroup.size(); k++) {
+            Job *j = sgroup[k];
+            s_off[k] = j->dev_off;
+            s_len[k] = j->n;
+            s_base[k] = sha_seg;
+            s_out[k] = j->dev_off + j->in_region;
+            sha_seg += (j->n + j->seg_bytes - 1) / j->seg_bytes;
+        }
+        s_base[sgroup.size()] = sha_seg;
         e = hipMemcpyAsync(dtab, h, kSlotBytes, hipMemcpyHostToDevice, L->stream_in);
     }
     if (e == hipSuccess)
@@ -335,6 +350,17 @@ static hipError_t enqueue_batch(Lib *L, Batch *b)
                        dtab + 3 * kTabN};
         e = launch_md5_segments(L->dev_slab, gjt, group[0]->seg_bytes, total_seg, L->dev_slab,
                                 st);
+        if (e != hipSuccess)
+            return e;
+    }
+    if (!sgroup.empty()) {
+        // SHA-1 direct jobs: one segment launch and one root launch for the group
+        const JobTable sjt{dtab + 9 * kTabN, dtab + 10 * kTabN, dtab + 11 * kTabN,
+                           (uint32_t)sgroup.size(), 0, dtab + 12 * kTabN};
+        e = launch_sha1_segments(L->dev_slab, sjt, sgroup[0]->seg_bytes, sha_seg, L->dev_slab,
+                                 st);
+        if (e == hipSuccess)
+            e = launch_sha1_roots(L->dev_slab, sjt, sgroup[0]->seg_bytes, L->dev_slab, st);
         if (e != hipSuccess)
             return e;
     }
@@ -360,6 +386,8 @@ static hipError_t enqueue_batch(Lib *L, Batch *b)
             break;
         }
         case CRYSTAL_K_SHA1_DIRECT: {
+            if (std::find(sgroup.begin(), sgroup.end(), j) != sgroup.end())
+                break; // hashed by the group launches above
             JobTable jt{nullptr, nullptr, nullptr, 0, j->n};
             const uint64_t nseg = (j->n + j->seg_bytes - 1) / j->seg_bytes;
             e = launch_sha1_segments(d_in, jt, j->seg_bytes, nseg, d_out, st);

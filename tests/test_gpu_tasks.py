@@ -293,6 +293,46 @@ def test_batched_chains_mixed_jobs(P, torch_cuda):
         P.crystal_finalize()
 
 
+def test_batched_sha1_and_md5_direct_jobs(P, torch_cuda):
+    """SHA-1 and MD5 direct jobs submitted at once share batches: each group
+    runs one segment launch (and the SHA-1 group one root launch).  Includes
+    empty, 1-byte and ragged jobs; every output equals the oracle's."""
+    torch = torch_cuda
+    P.crystal_init(max_input_bytes=4 << 20, host_pool_bytes=64 << 20,
+                   device_pool_bytes=1 << 30, n_streams=1, max_in_flight=32)
+    try:
+        rng = np.random.default_rng(91)
+        sizes = [0, 1, 0, 1, 4096 * 5 + 9] + [int(x) for x in
+                                               np.exp(rng.uniform(np.log(4096),
+                                                                  np.log(4 << 20), 35))]
+        sha = [1, 1, 0, 0, 1] + [int(k) for k in rng.random(35) < 0.6]
+        n = len(sizes)
+        offs = np.zeros(n, dtype=np.int64)
+        offs[1:] = np.cumsum([(x + 4095) // 4096 * 4096 for x in sizes[:-1]])
+        arena = torch.empty(int(offs[-1]) + sizes[-1] + 4096, dtype=torch.uint8).pin_memory()
+        gen.fill(616, arena.data_ptr(), arena.numel())
+        jobs, outs, direct, cdcp = _drive_jobs(P, torch, sizes, [0] * n, [0.0] * n, arena,
+                                               offs, gen.cdc_base())
+        for k in range(n):
+            if sha[k]:
+                jobs[k].kernel_id = P.K_SHA1_DIRECT
+                jobs[k].out_cap = P.crystal_output_bytes(P.K_SHA1_DIRECT, sizes[k], direct)
+                outs[k] = torch.empty(jobs[k].out_cap, dtype=torch.uint8).pin_memory()
+                jobs[k].h_out = outs[k].data_ptr()
+        res = P.crystal_drive(jobs, direct, cdcp, window=0)
+        assert res.ok == n and res.failed == 0
+        a = arena.numpy()
+        for k in range(n):
+            data = a[int(offs[k]):int(offs[k]) + sizes[k]]
+            mix = outs[k].numpy()
+            w = 20 if sha[k] else 16
+            es, er = (oracle.sha1_direct if sha[k] else oracle.direct)(data)
+            assert mix[:w * len(es)].tobytes() == es.tobytes(), k
+            assert mix[w * len(es):w * len(es) + w].tobytes() == er, k
+    finally:
+        P.crystal_finalize()
+
+
 def test_closed_loop_window(lib, torch_cuda):
     P, torch = lib, torch_cuda
     n = 24
