@@ -569,6 +569,33 @@ static void completer_main(Lib *L, int s)
     }
 }
 
+// HIP resources of a library instance that init created (or got as far as
+// creating); null handles are skipped.  Threads must be stopped already.
+static void release_resources(Lib *L)
+{
+    (void)hipSetDevice(L->device);
+    for (hipEvent_t ev : L->events)
+        (void)hipEventDestroy(ev);
+    L->events.clear();
+    if (L->own_streams) {
+        if (L->stream_in)
+            (void)hipStreamDestroy(L->stream_in);
+        for (hipStream_t s : L->streams)
+            if (s)
+                (void)hipStreamDestroy(s);
+    }
+    if (L->own_dev && L->dev_slab)
+        (void)hipFree(L->dev_slab);
+    if (L->host_slab)
+        (void)hipHostFree(L->host_slab);
+    if (L->table_host)
+        (void)hipHostFree(L->table_host);
+    if (L->table_dev)
+        (void)hipFree(L->table_dev);
+    L->dev_slab = L->host_slab = nullptr;
+    L->table_host = L->table_dev = nullptr;
+}
+
 static Lib *lib_or_fail()
 {
     Lib *L = g_lib;
@@ -628,6 +655,11 @@ int crystal_init(const crystal_config *cfg_in)
     std::unique_ptr<Lib> L(new Lib);
     L->cfg = cfg;
     L->device = cfg.device;
+    // on any failure below, what was created so far is released
+    auto bail = [&](int rc) {
+        release_resources(L.get());
+        return rc;
+    };
     hipError_t e = hipSetDevice(cfg.device);
     if (e != hipSuccess)
         return hip_fail(e, "hipSetDevice");
@@ -635,21 +667,22 @@ int crystal_init(const crystal_config *cfg_in)
         L->dev_slab = static_cast<uint8_t *>(cfg.device_slab);
     } else {
         e = hipMalloc((void **)&L->dev_slab, cfg.device_pool_bytes);
-        if (e != hipSuccess)
-            return fail(CRYSTAL_ENOMEM, "device slab of %zu bytes: %s", cfg.device_pool_bytes,
-                        hipGetErrorString(e));
+        if (e != hipSuccess) {
+            L->dev_slab = nullptr;
+            return bail(fail(CRYSTAL_ENOMEM, "device slab of %zu bytes: %s",
+                             cfg.device_pool_bytes, hipGetErrorString(e)));
+        }
         L->own_dev = true;
     }
     e = hipHostMalloc((void **)&L->host_slab, cfg.host_pool_bytes, hipHostMallocDefault);
     if (e != hipSuccess) {
-        if (L->own_dev)
-            (void)hipFree(L->dev_slab);
-        return fail(CRYSTAL_ENOMEM, "pinned host slab of %zu bytes: %s", cfg.host_pool_bytes,
-                    hipGetErrorString(e));
+        L->host_slab = nullptr;
+        return bail(fail(CRYSTAL_ENOMEM, "pinned host slab of %zu bytes: %s",
+                         cfg.host_pool_bytes, hipGetErrorString(e)));
     }
     L->dev_alloc.reset(cfg.device_pool_bytes);
     L->host_alloc.reset(cfg.host_pool_bytes);
-    L->streams.resize(cfg.n_streams);
+    L->streams.assign(cfg.n_streams, nullptr);
     if (cfg.streams) {
         L->stream_in = static_cast<hipStream_t>(cfg.streams[0]);
         for (uint32_t s = 0; s < cfg.n_streams; s++)
@@ -657,26 +690,33 @@ int crystal_init(const crystal_config *cfg_in)
     } else {
         L->own_streams = true;
         e = hipStreamCreateWithFlags(&L->stream_in, hipStreamNonBlocking);
-        for (uint32_t s = 0; s < cfg.n_streams && e == hipSuccess; s++)
-            e = hipStreamCreateWithFlags(&L->streams[s], hipStreamNonBlocking);
         if (e != hipSuccess)
-            return hip_fail(e, "hipStreamCreate");
+            L->stream_in = nullptr;
+        for (uint32_t s = 0; s < cfg.n_streams && e == hipSuccess; s++)
+            if ((e = hipStreamCreateWithFlags(&L->streams[s], hipStreamNonBlocking)) !=
+                hipSuccess)
+                L->streams[s] = nullptr;
+        if (e != hipSuccess)
+            return bail(hip_fail(e, "hipStreamCreate"));
     }
     const uint32_t n_ev = 2 * (cfg.max_in_flight + 1);
     for (uint32_t i = 0; i < n_ev; i++) {
         hipEvent_t ev;
         e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e != hipSuccess)
-            return hip_fail(e, "hipEventCreate");
+            return bail(hip_fail(e, "hipEventCreate"));
         L->events.push_back(ev);
         L->free_events.push_back(ev);
     }
     const uint32_t n_slots = cfg.max_in_flight + 1;
     e = hipHostMalloc((void **)&L->table_host, n_slots * kSlotBytes, hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipMalloc((void **)&L->table_dev, n_slots * kSlotBytes);
     if (e != hipSuccess)
-        return fail(CRYSTAL_ENOMEM, "job-table ring: %s", hipGetErrorString(e));
+        L->table_host = nullptr;
+    if (e == hipSuccess && (e = hipMalloc((void **)&L->table_dev, n_slots * kSlotBytes)) !=
+                               hipSuccess)
+        L->table_dev = nullptr;
+    if (e != hipSuccess)
+        return bail(fail(CRYSTAL_ENOMEM, "job-table ring: %s", hipGetErrorString(e)));
     for (uint32_t i = 0; i < n_slots; i++)
         L->free_slots.push_back((int)i);
     L->running.resize(cfg.n_streams);
@@ -722,19 +762,7 @@ int crystal_finalize(void)
         cv->notify_all();
     for (auto &th : L->completers)
         th.join();
-    (void)hipSetDevice(L->device);
-    for (hipEvent_t ev : L->events)
-        (void)hipEventDestroy(ev);
-    if (L->own_streams) {
-        (void)hipStreamDestroy(L->stream_in);
-        for (hipStream_t s : L->streams)
-            (void)hipStreamDestroy(s);
-    }
-    if (L->own_dev)
-        (void)hipFree(L->dev_slab);
-    (void)hipHostFree(L->host_slab);
-    (void)hipHostFree(L->table_host);
-    (void)hipFree(L->table_dev);
+    release_resources(L);
     for (crystal_buf *b : L->bufs)
         delete b;
     g_lib = nullptr;
