@@ -560,7 +560,8 @@ def batch(P, torch, gen, n_buf, reps=20, sample_single=20000):
     return out("batch", {
         "buffers": n_buf, "bytes": total, "compressions": comps,
         "tuning": {"block": tun.block, "waves_per_simd": tun.waves_per_simd, "grab": tun.grab,
-                   "streams": tun.n_streams, "sorted": tun.sorted,
+                   "streams": tun.n_streams, "sorted": tun.sorted, "depth": tun.depth,
+                   "tail": tun.tail,
                    "tuned_replay_ms": round(tun.replay_ms, 4)},
         "plan_seconds": round(plan_s, 2),
         "replay_ms": round(ms, 4), "gbps": round(total / 1e9 / (ms / 1e3), 1),

@@ -325,7 +325,7 @@ typedef struct crystal_batch_desc {
 } crystal_batch_desc;
 
 typedef struct crystal_batch_tuning {
-    uint32_t block;          /* workgroup size */
+    uint32_t block;          /* workgroup size: 64, 128, 192 or 256 */
     uint32_t waves_per_simd; /* persistent grid = 256 CUs x 4 SIMDs x this */
     uint32_t grab;           /* buffers a wave takes per work-counter grab,
                                 in units of 64 */
@@ -333,6 +333,12 @@ typedef struct crystal_batch_tuning {
     uint32_t sorted;         /* lane order: 0 = index order, 1 = longest first
                                 over the whole batch, W > 1 = longest first
                                 within each run of W consecutive buffers */
+    uint32_t depth;          /* loader depth: 128-byte groups per lane read
+                                ahead of its compression, 1..3 (0 = 2) */
+    uint32_t tail;           /* the last `tail` entries of the lane order
+                                are re-sorted longest first as one block, so
+                                the launch ends on its shortest buffers
+                                (0 = no re-sort; clamped to n_buf) */
     float replay_ms;         /* measured time of one replay */
 } crystal_batch_tuning;
 
@@ -342,7 +348,9 @@ typedef struct crystal_batch crystal_batch;
 #define CRYSTAL_TUNE_FULL 1  /* grid search, replay-timed */
 
 /* Build a plan: length-sort the buffers (longest first), choose launch
- * parameters (tune_flags) by timing replays.
+ * parameters (tune_flags) by timing replays.  CRYSTAL_TUNE_FULL searches the
+ * loader depth, waves per SIMD, workgroup size and sort window, with a tail
+ * of four rounds of resident lanes.
  * The library allocates the plan's own small device tables.  *fixed may be
  * NULL. */
 int crystal_batch_plan(const crystal_batch_desc *d, int tune_flags,

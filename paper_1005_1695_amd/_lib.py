@@ -72,7 +72,8 @@ class crystal_batch_desc(ctypes.Structure):
 
 class crystal_batch_tuning(ctypes.Structure):
     _fields_ = [("block", c_u32), ("waves_per_simd", c_u32), ("grab", c_u32),
-                ("n_streams", c_u32), ("sorted", c_u32), ("replay_ms", ctypes.c_float)]
+                ("n_streams", c_u32), ("sorted", c_u32), ("depth", c_u32), ("tail", c_u32),
+                ("replay_ms", ctypes.c_float)]
 
 
 class crystal_stage_times(ctypes.Structure):

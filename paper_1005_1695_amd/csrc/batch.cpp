@@ -4,6 +4,15 @@
 // split over several streams as parallel branches joined by events).  The
 // tuner times every candidate configuration by replay.
 //
+// Lane order.  Longest-first inside windows of W consecutive buffers gives
+// each wave 64 near-equal lengths that lie close together in the arena (a
+// global sort spreads every wave over the whole arena and runs at less than
+// half the speed).  But a window holds fewer groups of 64 than there are
+// waves in flight, so the last windows' longest groups would start at the
+// very end and leave most SIMDs idle while they finish.  The plan therefore
+// re-sorts the last `tail` entries longest first as one block: with a tail of
+// a few rounds of resident lanes the launch ends on its shortest buffers.
+//
 // Replay uses direct stream launches.  Capturing the same sequence into a HIP
 // graph (capture() below) is switched off: under the HIP runtime that PyTorch
 // loads into the process, a plan built that way ended in a host segmentation
@@ -23,6 +32,7 @@ struct crystal_batch {
     uint32_t n_simd;
     std::vector<uint32_t> len;     // host copy of the lengths
     uint32_t order_window = 0;     // sort window the device order holds
+    uint64_t order_tail = 0;       // tail re-sort the device order holds
     uint32_t *d_order = nullptr;
     uint32_t *d_counters = nullptr;
     std::vector<uint64_t> work_prefix; // compressions, prefix over sorted order
@@ -46,7 +56,9 @@ static void destroy_graph(crystal_batch *b)
     b->graph = nullptr;
 }
 
-static hipError_t set_order(crystal_batch *b, uint32_t W);
+static hipError_t set_order(crystal_batch *b, uint32_t W, uint64_t T);
+
+static bool uses_order(const crystal_batch_tuning &t) { return t.sorted != 0 || t.tail != 0; }
 
 // Capture zero-counter + persistent kernel per branch.  Branch i covers a
 // contiguous slice of the order holding about 1/S of the total work.
@@ -59,8 +71,8 @@ static hipError_t capture(crystal_batch *b, const crystal_batch_tuning &t)
     uint32_t grid = (uint32_t)((uint64_t)waves * 64 / t.block);
     if (grid == 0)
         grid = 1;
-    const uint32_t *order = t.sorted ? b->d_order : nullptr;
-    hipError_t e = t.sorted ? set_order(b, t.sorted) : hipSuccess;
+    const uint32_t *order = uses_order(t) ? b->d_order : nullptr;
+    hipError_t e = set_order(b, t.sorted, t.tail);
     if (e == hipSuccess)
         e = hipStreamBeginCapture(b->cap[0], hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess)
@@ -88,14 +100,14 @@ static hipError_t capture(crystal_batch *b, const crystal_batch_tuning &t)
                 e = launch_md5_batch_persistent((const uint8_t *)b->d.d_arena, b->d.d_off,
                                                 b->d.d_len, ord, hi - lo,
                                                 (uint8_t *)b->d.d_out, b->d_counters + i,
-                                                t.grab, t.block, g, b->cap[i]);
+                                                t.grab, t.depth, t.block, g, b->cap[i]);
             } else {
                 // index order: slice offsets directly
                 e = launch_md5_batch_persistent((const uint8_t *)b->d.d_arena,
                                                 b->d.d_off + lo, b->d.d_len + lo, nullptr,
                                                 hi - lo, (uint8_t *)b->d.d_out + 16 * lo,
-                                                b->d_counters + i, t.grab, t.block, g,
-                                                b->cap[i]);
+                                                b->d_counters + i, t.grab, t.depth, t.block,
+                                                g, b->cap[i]);
             }
         }
         lo = hi;
@@ -132,20 +144,8 @@ static hipError_t launch_direct(crystal_batch *b, const crystal_batch_tuning &t)
     uint32_t grid = (uint32_t)((uint64_t)waves * 64 / t.block);
     if (grid == 0)
         grid = 1;
-    const uint32_t *order = t.sorted ? b->d_order : nullptr;
-    hipError_t e = hipSuccess;
-    if (!t.sorted) { // work prefix of the index order
-        uint64_t acc = 0;
-        if (b->order_window != 0) {
-            for (uint64_t i = 0; i < n; i++) {
-                acc += (b->len[i] + 8) / 64 + 1;
-                b->work_prefix[i] = acc;
-            }
-            b->order_window = 0;
-        }
-    } else {
-        e = set_order(b, t.sorted);
-    }
+    const uint32_t *order = uses_order(t) ? b->d_order : nullptr;
+    hipError_t e = set_order(b, t.sorted, t.tail);
     if (S > 1 && e == hipSuccess) {
         e = hipEventRecord(b->ev[0], s0);
         for (uint32_t i = 1; i < S && e == hipSuccess; i++)
@@ -169,12 +169,13 @@ static hipError_t launch_direct(crystal_batch *b, const crystal_batch_tuning &t)
                 e = launch_md5_batch_persistent((const uint8_t *)b->d.d_arena, b->d.d_off,
                                                 b->d.d_len, order + lo, hi - lo,
                                                 (uint8_t *)b->d.d_out, b->d_counters + i,
-                                                t.grab, t.block, g, si);
+                                                t.grab, t.depth, t.block, g, si);
             else
                 e = launch_md5_batch_persistent((const uint8_t *)b->d.d_arena,
                                                 b->d.d_off + lo, b->d.d_len + lo, nullptr,
                                                 hi - lo, (uint8_t *)b->d.d_out + 16 * lo,
-                                                b->d_counters + i, t.grab, t.block, g, si);
+                                                b->d_counters + i, t.grab, t.depth, t.block,
+                                                g, si);
         }
         lo = hi;
     }
@@ -188,32 +189,41 @@ static hipError_t launch_direct(crystal_batch *b, const crystal_batch_tuning &t)
     return e;
 }
 
-// Lane order for a sort window W: W == 1 sorts the whole batch longest
-// first; W > 1 sorts longest first inside each run of W consecutive buffers,
-// so the 64 buffers a wave takes have nearly equal lengths (little lockstep
-// waste) and still lie close together in the arena.  Also rebuilds the work
-// prefix used to split the order across branches.
-static hipError_t set_order(crystal_batch *b, uint32_t W)
+// Lane order for sort window W and tail T: W == 0 keeps index order, W == 1
+// sorts the whole batch longest first, W > 1 sorts longest first inside each
+// run of W consecutive buffers; then the last min(T, n) entries are re-sorted
+// longest first as one block.  Also rebuilds the work prefix used to split
+// the order across branches.  The device order is written only when the
+// order differs from index order.
+static hipError_t set_order(crystal_batch *b, uint32_t W, uint64_t T)
 {
-    if (W == 0 || W == b->order_window)
-        return hipSuccess;
     const uint64_t n = b->d.n_buf;
+    T = std::min<uint64_t>(T, n);
+    if (b->order_window == W && b->order_tail == T)
+        return hipSuccess;
     std::vector<uint32_t> order(n);
     std::iota(order.begin(), order.end(), 0u);
-    const uint64_t win = W == 1 ? n : W;
-    for (uint64_t lo = 0; lo < n; lo += win) {
-        const uint64_t hi = std::min<uint64_t>(n, lo + win);
-        std::stable_sort(order.begin() + lo, order.begin() + hi,
-                         [&](uint32_t x, uint32_t y) { return b->len[x] > b->len[y]; });
+    auto longer = [&](uint32_t x, uint32_t y) { return b->len[x] > b->len[y]; };
+    if (W != 0) {
+        const uint64_t win = W == 1 ? n : W;
+        for (uint64_t lo = 0; lo < n; lo += win)
+            std::stable_sort(order.begin() + lo,
+                             order.begin() + std::min<uint64_t>(n, lo + win), longer);
     }
+    if (T > 1)
+        std::stable_sort(order.end() - T, order.end(), longer);
     uint64_t acc = 0;
     for (uint64_t i = 0; i < n; i++) {
         acc += (b->len[order[i]] + 8) / 64 + 1;
         b->work_prefix[i] = acc;
     }
-    hipError_t e = hipMemcpy(b->d_order, order.data(), 4 * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
+    hipError_t e = hipSuccess;
+    if (W != 0 || T != 0)
+        e = hipMemcpy(b->d_order, order.data(), 4 * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
         b->order_window = W;
+        b->order_tail = T;
+    }
     return e;
 }
 
@@ -304,6 +314,8 @@ int crystal_batch_plan(const crystal_batch_desc *d, int tune_flags,
         acc += (b->len[i] + 8) / 64 + 1;
         b->work_prefix[i] = acc;
     }
+    b->order_window = 0; // the work prefix above is the index order's
+    b->order_tail = 0;
     e = hipMalloc((void **)&b->d_order, 4 * d->n_buf);
     if (e == hipSuccess)
         e = hipMalloc((void **)&b->d_counters, 4 * kMaxBranches);
@@ -316,30 +328,39 @@ int crystal_batch_plan(const crystal_batch_desc *d, int tune_flags,
         return hip_fail(e, "plan setup");
     }
 
+    // a tail of four rounds of resident lanes
+    auto tail_for = [&](uint32_t wps) { return 4u * b->n_simd * wps * 64u; };
     std::vector<crystal_batch_tuning> cands;
-    crystal_batch_tuning def = {256, 4, 1, 1, 4096, 0.f};
+    crystal_batch_tuning def = {256, 1, 1, 1, 4096, 2, tail_for(1), 0.f};
     if (fixed) {
         def = *fixed;
         if (def.block == 0)
             def.block = 256;
         if (def.waves_per_simd == 0)
-            def.waves_per_simd = 4;
+            def.waves_per_simd = 1;
         if (def.grab == 0)
             def.grab = 1;
         if (def.n_streams == 0)
             def.n_streams = 1;
+        if (def.depth == 0)
+            def.depth = 2;
     }
-    if (def.block % 64 || def.block > 1024 || def.n_streams > kMaxBranches) {
+    if (def.block % 64 || def.block == 0 || def.block > 256 || def.depth > 3 ||
+        def.n_streams > kMaxBranches) {
         free_plan(b);
-        return fail(CRYSTAL_EINVAL, "bad tuning: block %% 64, <= 1024; streams <= 8");
+        return fail(CRYSTAL_EINVAL,
+                    "bad tuning: block a multiple of 64 up to 256; depth 1..3; streams <= 8");
     }
     if (tune_flags == CRYSTAL_TUNE_FULL) {
-        for (uint32_t sorted : {256u, 1024u, 4096u, 65536u, 1u, 0u})
-            for (uint32_t S : {1u, 2u})
-                for (uint32_t blk : {64u, 256u})
-                    for (uint32_t wps : {2u, 4u, 8u})
-                        for (uint32_t grab : {1u, 4u})
-                            cands.push_back({blk, wps, grab, S, sorted, 0.f});
+        // (loader depth, waves per SIMD) pairs that fit the depth's register
+        // budget; grouped by order so each order is built once
+        const uint32_t dw[][2] = {{1, 2}, {1, 4}, {2, 1}, {2, 2}, {2, 3}, {3, 1}, {3, 2}};
+        for (uint32_t sorted : {4096u, 65536u})
+            for (uint32_t wps : {1u, 2u, 3u, 4u})
+                for (const auto &p : dw)
+                    if (p[1] == wps)
+                        for (uint32_t blk : {64u, 256u})
+                            cands.push_back({blk, wps, 1, 1, sorted, p[0], tail_for(wps), 0.f});
     } else {
         cands.push_back(def);
     }

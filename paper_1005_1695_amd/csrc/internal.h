@@ -45,7 +45,7 @@ hipError_t launch_md5_batch(const uint8_t *arena, const uint64_t *off,
 hipError_t launch_md5_batch_persistent(const uint8_t *arena, const uint64_t *off,
                                        const uint32_t *len, const uint32_t *order,
                                        uint64_t n, uint8_t *out, uint32_t *counter,
-                                       uint32_t grab, uint32_t block,
+                                       uint32_t grab, uint32_t depth, uint32_t block,
                                        uint32_t grid, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t s);
 // Digest of each chunk; lane i takes chunk order[i] (order == nullptr: chunk i).

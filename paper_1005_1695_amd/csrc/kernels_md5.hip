@@ -160,15 +160,43 @@ __global__ void k_md5_batch(const uint8_t *__restrict__ arena,
     }
 }
 
+// One buffer of a batch with a loader that keeps D 128-byte groups per lane
+// in flight ahead of the compression.  Deeper look-ahead means fewer, larger
+// reads per lane: on the batch's scattered per-lane streams this raises the
+// bandwidth the memory system delivers, at the cost of registers.
+template <int D>
+__device__ __forceinline__ void md5_one_buffer_d(const uint8_t *__restrict__ arena,
+                                                 const uint64_t *__restrict__ off,
+                                                 const uint32_t *__restrict__ len, uint64_t m,
+                                                 uint8_t *__restrict__ out)
+{
+    const uint8_t *p = arena + off[m];
+    const uint64_t l = len[m];
+    uint32_t st[4];
+    if (((uintptr_t)p & 15) == 0)
+        md5_message_a16_db<D>(p, l, st);
+    else
+        md5_message_any(p, l, st);
+    md5_store(out + 16 * m, st);
+}
+
+// Register budget per depth: D = 1 fits 4 waves per SIMD, D = 2 three and
+// D = 3 two.
+template <int D> struct BatchWaves;
+template <> struct BatchWaves<1> { static constexpr int value = 4; };
+template <> struct BatchWaves<2> { static constexpr int value = 3; };
+template <> struct BatchWaves<3> { static constexpr int value = 2; };
+
 // Persistent batch: each wave repeatedly takes the next grab*64 entries of
 // the (longest-first) order from a global counter, so waves that drew short
 // buffers come back for more.  Every wave leaves once the counter passes n.
-__global__ void k_md5_batch_persistent(const uint8_t *__restrict__ arena,
-                                       const uint64_t *__restrict__ off,
-                                       const uint32_t *__restrict__ len,
-                                       const uint32_t *__restrict__ order,
-                                       uint64_t n, uint8_t *__restrict__ out,
-                                       uint32_t *__restrict__ counter, uint32_t grab)
+template <int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BatchWaves<D>::value)))
+void k_md5_batch_persistent(const uint8_t *__restrict__ arena, const uint64_t *__restrict__ off,
+                            const uint32_t *__restrict__ len,
+                            const uint32_t *__restrict__ order, uint64_t n,
+                            uint8_t *__restrict__ out, uint32_t *__restrict__ counter,
+                            uint32_t grab)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t span = grab * 64u;
@@ -183,7 +211,7 @@ __global__ void k_md5_batch_persistent(const uint8_t *__restrict__ arena,
             const uint64_t i = (uint64_t)base + 64u * k + lane;
             if (i < n) {
                 const uint64_t m = order ? order[i] : i;
-                md5_one_buffer(arena, off, len, m, out);
+                md5_one_buffer_d<D>(arena, off, len, m, out);
             }
         }
     }
@@ -334,13 +362,22 @@ hipError_t launch_md5_batch(const uint8_t *arena, const uint64_t *off,
 hipError_t launch_md5_batch_persistent(const uint8_t *arena, const uint64_t *off,
                                        const uint32_t *len, const uint32_t *order,
                                        uint64_t n, uint8_t *out, uint32_t *counter,
-                                       uint32_t grab, uint32_t block,
+                                       uint32_t grab, uint32_t depth, uint32_t block,
                                        uint32_t grid, hipStream_t s)
 {
     if (n == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_md5_batch_persistent, dim3(grid), dim3(block), 0, s, arena,
-                       off, len, order, n, out, counter, grab);
+    if (block == 0 || block > 256 || block % 64 || depth < 1 || depth > 3)
+        return hipErrorInvalidValue;
+    if (depth == 1)
+        hipLaunchKernelGGL(k_md5_batch_persistent<1>, dim3(grid), dim3(block), 0, s, arena,
+                           off, len, order, n, out, counter, grab);
+    else if (depth == 2)
+        hipLaunchKernelGGL(k_md5_batch_persistent<2>, dim3(grid), dim3(block), 0, s, arena,
+                           off, len, order, n, out, counter, grab);
+    else
+        hipLaunchKernelGGL(k_md5_batch_persistent<3>, dim3(grid), dim3(block), 0, s, arena,
+                           off, len, order, n, out, counter, grab);
     return hipGetLastError();
 }
 

@@ -435,8 +435,17 @@ def test_batch_plan_replays(P, torch_cuda):
             P.crystal_batch_free(plan)
 
 
-def test_batch_plan_fixed_multi_stream(P, torch_cuda):
+# (sorted, depth, tail, waves_per_simd, n_streams): index order and global
+# order, every loader depth, tails shorter than, equal to and longer than the
+# batch, alone and split over branches
+FIXED_PLANS = [(0, 1, 0, 2, 4), (1, 2, 0, 2, 4), (0, 3, 1000, 2, 1), (64, 2, 5000, 1, 2),
+               (256, 1, 4096, 4, 1), (4096, 3, 100000, 1, 3), (64, 2, 1, 3, 1)]
+
+
+@pytest.mark.parametrize("cfg", FIXED_PLANS, ids=lambda c: "s%d_d%d_t%d_w%d_b%d" % c)
+def test_batch_plan_fixed_multi_stream(P, torch_cuda, cfg):
     torch = torch_cuda
+    sorted_, depth, tail, wps, branches = cfg
     off, ln, arena, seed = gen.batch_small(n_buf=5000, seed=8)
     data = gen.random_bytes(seed, arena + 64)
     d, _ = P.to_device_bytes(data)
@@ -444,20 +453,35 @@ def test_batch_plan_fixed_multi_stream(P, torch_cuda):
     t_len = torch.from_numpy(ln.view(np.int32)).cuda()
     out = torch.zeros((5000, 16), dtype=torch.uint8, device="cuda")
     exp = oracle.md5_batch(data, off, ln)
-    for sorted_ in (0, 1):
-        fixed = P.crystal_batch_tuning(block=128, waves_per_simd=2, grab=4, n_streams=4,
-                                       sorted=sorted_)
-        s = torch.cuda.Stream()
-        plan = P.crystal_batch_plan(d, t_off, t_len, 5000, out, stream=s, fixed=fixed)
-        try:
-            for rep in range(2):
-                with torch.cuda.stream(s):
-                    out.zero_()
-                    P.crystal_batch_run(plan, 1)
-                s.synchronize()
-                assert np.array_equal(out.cpu().numpy(), exp)
-        finally:
-            P.crystal_batch_free(plan)
+    fixed = P.crystal_batch_tuning(block=128, waves_per_simd=wps, grab=4, n_streams=branches,
+                                   sorted=sorted_, depth=depth, tail=tail)
+    s = torch.cuda.Stream()
+    plan = P.crystal_batch_plan(d, t_off, t_len, 5000, out, stream=s, fixed=fixed)
+    try:
+        for rep in range(2):
+            with torch.cuda.stream(s):
+                out.zero_()
+                P.crystal_batch_run(plan, 1)
+            s.synchronize()
+            assert np.array_equal(out.cpu().numpy(), exp), rep
+    finally:
+        P.crystal_batch_free(plan)
+
+
+@pytest.mark.parametrize("bad", [dict(block=512), dict(block=96), dict(depth=4),
+                                 dict(n_streams=9)])
+def test_batch_plan_rejects_bad_tuning(P, torch_cuda, bad):
+    torch = torch_cuda
+    off, ln, arena, seed = gen.batch_small(n_buf=100, seed=3)
+    data = gen.random_bytes(seed, arena + 64)
+    d, _ = P.to_device_bytes(data)
+    t_off = torch.from_numpy(off.view(np.int64)).cuda()
+    t_len = torch.from_numpy(ln.view(np.int32)).cuda()
+    out = torch.zeros((100, 16), dtype=torch.uint8, device="cuda")
+    fixed = P.crystal_batch_tuning(**bad)
+    with pytest.raises(P.CrystalError) as ei:
+        P.crystal_batch_plan(d, t_off, t_len, 100, out, fixed=fixed)
+    assert ei.value.code == P._lib.EINVAL
 
 
 def test_batch_plan_full_size_sampled(P, torch_cuda):
