@@ -81,8 +81,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 
 // Lane j computes the root of job j: MD5 over its segment digests, which are
 // contiguous and 16-byte aligned in the digest array.  Each lane is one long
-// serial chain with few waves around it, so its loader double-buffers two
-// 128-byte groups at a time.  (Raising these waves' issue priority was measured to
+// serial chain with few waves around it, usually beside a segment kernel that
+// keeps HBM busy; load latency is then several microseconds, so its loader
+// reads three 128-byte groups (six compressions) ahead.  (Raising these waves' issue priority was measured to
 // slow a concurrently running segment kernel by far more than it sped the
 // chains up, so they run at the default priority.)
 __device__ __forceinline__ void md5_root_of_job(const uint8_t *__restrict__ dig,
@@ -103,7 +104,7 @@ __device__ __forceinline__ void md5_root_of_job(const uint8_t *__restrict__ dig,
         dst = const_cast<uint8_t *>(src) + 16 * nseg;
     }
     uint32_t st[4];
-    md5_message_a16_db<2>(src, 16 * nseg, st);
+    md5_message_a16_db<3>(src, 16 * nseg, st);
     md5_store(dst, st);
 }
 
