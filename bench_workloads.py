@@ -564,7 +564,9 @@ def batch(P, torch, gen, n_buf, reps=20, sample_single=20000):
                    "tail": tun.tail,
                    "tuned_replay_ms": round(tun.replay_ms, 4)},
         "plan_seconds": round(plan_s, 2),
-        "replay_ms": round(ms, 4), "gbps": round(total / 1e9 / (ms / 1e3), 1),
+        "replay_ms": round(ms, 4), "replay_ms_median": round(statistics.median(times), 4),
+        "replay_ms_min": round(min(times), 4),
+        "gbps": round(total / 1e9 / (ms / 1e3), 1),
         "alu_tops": round(ops / (ms / 1e3) / 1e12, 2),
         "alu_frac": round(ops / (ms / 1e3) / 1e12 / INT32_PEAK_TOPS, 4),
         "hbm_frac": round(total / 1e9 / (ms / 1e3) / HBM_PEAK_GBPS, 4),

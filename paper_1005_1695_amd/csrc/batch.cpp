@@ -360,7 +360,9 @@ int crystal_batch_plan(const crystal_batch_desc *d, int tune_flags,
                 for (const auto &p : dw)
                     if (p[1] == wps)
                         for (uint32_t blk : {64u, 256u})
-                            cands.push_back({blk, wps, 1, 1, sorted, p[0], tail_for(wps), 0.f});
+                            for (uint32_t S : {1u, 2u})
+                                cands.push_back({blk, wps, 1, S, sorted, p[0], tail_for(wps),
+                                                 0.f});
     } else {
         cands.push_back(def);
     }
