@@ -32,6 +32,7 @@ import json
 import math
 import os
 import statistics
+import subprocess
 import sys
 import time
 
@@ -589,14 +590,35 @@ def main() -> int:
     ap.add_argument("--batch-buffers", type=int, default=0)
     ap.add_argument("--sha1-streams", type=int, default=3)
     ap.add_argument("--sha1-window", type=int, default=24)
+    ap.add_argument("--in-process", action="store_true",
+                    help="run all selected workloads in this process (by default each "
+                         "workload runs in a fresh child process)")
     args = ap.parse_args()
+    names = ["direct_one", "overhead", "naive_stages", "stream_len", "sha1_stream",
+             "chunking", "batch", "serving"]
+    only = [x for x in args.only.split(",") if x]
+    if len(only) != 1 and not args.in_process:
+        # one process per workload: measured in the same process, the serving
+        # mix ran well below its rate when it followed other large workloads
+        rest = [a for a in sys.argv[1:] if not a.startswith("--only")]
+        if "--only" in sys.argv:
+            i = sys.argv.index("--only")
+            rest = sys.argv[1:i] + sys.argv[i + 2:]
+        rc = 0
+        for n in names:
+            if only and n not in only:
+                continue
+            r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--only", n,
+                                *rest])
+            rc = rc or r.returncode
+        return rc
     import torch
 
     import gen
     import paper_1005_1695_amd as P
     P.load()
     torch.cuda.set_device(0)
-    only = set(x for x in args.only.split(",") if x)
+    only = set(only)
     want = lambda n: not only or n in only
     if want("direct_one"):
         direct_one(P, torch, gen)
