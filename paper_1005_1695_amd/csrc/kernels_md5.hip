@@ -226,9 +226,11 @@ __global__ void k_zero_u32(uint32_t *p, uint32_t n)
 }
 
 // Digest of chunk k, the bytes [ends[k-1], ends[k]); chunk starts are
-// arbitrary byte offsets, so the realigning loader is used.  With dig ==
-// nullptr the digest goes right after the ends array (ends + nc), the packed
-// job output layout; that address is only 8-byte aligned.
+// arbitrary byte offsets, so the realigning loader is used, reading three
+// 128-byte groups ahead (the kernels that run these chains hold few waves, so
+// the registers are free).  With dig == nullptr the digest goes right after
+// the ends array (ends + nc), the packed job output layout; that address is
+// only 8-byte aligned.
 __device__ __forceinline__ void md5_one_chunk(const uint8_t *__restrict__ in,
                                               const uint64_t *__restrict__ ends, uint64_t nc,
                                               uint64_t k, uint8_t *__restrict__ dig)
@@ -236,7 +238,7 @@ __device__ __forceinline__ void md5_one_chunk(const uint8_t *__restrict__ in,
     const uint64_t lo = k ? ends[k - 1] : 0;
     const uint64_t hi = ends[k];
     uint32_t st[4];
-    md5_message_any_db<2>(in + lo, hi - lo, st);
+    md5_message_any_db<3>(in + lo, hi - lo, st);
     if (dig) {
         md5_store(dig + 16 * k, st);
     } else {
@@ -318,6 +320,7 @@ static inline uint32_t blocks_for(uint64_t n, uint32_t b)
 
 // Grid cap of the segment kernel (lanes); launches beyond it loop.
 static const uint64_t kSegMaxLanes = (uint64_t)1 << 30;
+static const uint64_t kOneWavePerSimd = 256 * 4 * 64;
 
 hipError_t launch_md5_segments(const uint8_t *in, const JobTable &jt,
                                uint32_t seg_bytes, uint64_t n_segments,
@@ -326,8 +329,12 @@ hipError_t launch_md5_segments(const uint8_t *in, const JobTable &jt,
     if (n_segments == 0)
         return hipSuccess;
     const uint64_t lanes = n_segments < kSegMaxLanes ? n_segments : kSegMaxLanes;
-    hipLaunchKernelGGL(k_md5_segments, dim3(blocks_for(lanes, 256)), dim3(256), 0, s, in, jt,
-                       seg_bytes, n_segments, seg_digests);
+    // launches of at most one wave per SIMD (256 CUs x 4 SIMDs x 64 lanes)
+    // spread over more CUs in single-wave groups: 4-7 % faster measured
+    // there; larger launches are not sensitive to the group size
+    const uint32_t block = lanes <= kOneWavePerSimd ? 64 : 256;
+    hipLaunchKernelGGL(k_md5_segments, dim3(blocks_for(lanes, block)), dim3(block), 0, s, in,
+                       jt, seg_bytes, n_segments, seg_digests);
     return hipGetLastError();
 }
 
