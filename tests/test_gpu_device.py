@@ -61,6 +61,29 @@ def test_direct_ragged_jobs(P, torch_cuda):
         assert roots[j].tobytes() == er, j
 
 
+def test_direct_root_loader_boundaries(P, torch_cuda):
+    """Jobs whose digest arrays (16 bytes per segment) end on each side of
+    the root loader's 64-byte block, 128-byte group and 384-byte chunk
+    boundaries, with a ragged last segment in every other job, in one
+    launch: segments and roots equal the oracle's."""
+    nsegs = [1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 23, 24, 25, 31, 32, 33, 47, 48, 49, 71, 72,
+             73, 95, 96, 97]
+    lens = [k * 4096 - (1000 if i % 2 else 0) for i, k in enumerate(nsegs)]
+    offs, o = [], 0
+    for ln in lens:
+        o = (o + 15) // 16 * 16
+        offs.append(o)
+        o += ln
+    arena = gen.random_bytes(321, o + 64)
+    d, _ = P.to_device_bytes(arena)
+    seg, roots, base, _ = P.direct_device(d, offs, lens)
+    seg, roots = _np(seg), _np(roots)
+    for j, (of, ln) in enumerate(zip(offs, lens)):
+        es, er = oracle.direct(arena[of:of + ln])
+        assert np.array_equal(seg[int(base[j]):int(base[j + 1])], es), j
+        assert roots[j].tobytes() == er, (j, nsegs[j])
+
+
 @pytest.mark.parametrize("segment", [64, 128, 4096, 65536])
 def test_direct_segment_sizes(P, torch_cuda, segment):
     data = gen.random_bytes(segment, 300001)

@@ -468,6 +468,61 @@ def test_batch_plan_fixed_multi_stream(P, torch_cuda, cfg):
         P.crystal_batch_free(plan)
 
 
+def _edge_batch(aligned: bool):
+    """Buffers whose lengths straddle every loader boundary: 64-byte blocks,
+    128-byte groups and chunks of 1, 2 and 3 groups (plus the 55/56 padding
+    edges), and empty buffers; 16-byte aligned starts, or starts at every
+    byte offset."""
+    base = [0, 1, 15, 16, 55, 56, 63, 64, 65, 119, 120, 127, 128, 129]
+    for c in (256, 384, 512, 768, 1152):
+        base += [c - 65, c - 64, c - 1, c, c + 1, c + 55, c + 56, c + 63, c + 64, c + 127]
+    base += [4096, 5000, 16383]
+    lens = np.array(base * 3, dtype=np.uint32)
+    off = np.zeros(len(lens), dtype=np.uint64)
+    pos = 0
+    for i, L in enumerate(lens):
+        if aligned:
+            pos = (pos + 15) // 16 * 16
+        else:
+            pos += 1 + (i % 7)
+        off[i] = pos
+        pos += int(L)
+    return off, lens, pos
+
+
+@pytest.mark.parametrize("aligned", [True, False], ids=["a16", "any"])
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_batch_plan_edges_every_depth(P, torch_cuda, depth, aligned):
+    """The persistent kernel behind batch plans, at every loader depth, on
+    buffers at the loader's block, group and chunk boundaries, empty
+    buffers included, with and without a tail re-sort and over 1 or 2
+    branches: every digest equals the oracle's."""
+    torch = torch_cuda
+    off, ln, end = _edge_batch(aligned)
+    data = gen.random_bytes(777, end + 64)
+    d, _ = P.to_device_bytes(data)
+    t_off = torch.from_numpy(off.view(np.int64)).cuda()
+    t_len = torch.from_numpy(ln.view(np.int32)).cuda()
+    n = len(ln)
+    exp = oracle.md5_batch(data, off, ln)
+    out = torch.zeros((n, 16), dtype=torch.uint8, device="cuda")
+    for sorted_, tail, branches in ((64, 0, 1), (0, n, 2), (1, 37, 1)):
+        fixed = P.crystal_batch_tuning(block=64, waves_per_simd=1, grab=1, n_streams=branches,
+                                       sorted=sorted_, depth=depth, tail=tail)
+        s = torch.cuda.Stream()
+        plan = P.crystal_batch_plan(d, t_off, t_len, n, out, stream=s, fixed=fixed)
+        try:
+            with torch.cuda.stream(s):
+                out.zero_()
+                P.crystal_batch_run(plan, 1)
+            s.synchronize()
+            got = out.cpu().numpy()
+            bad = [i for i in range(n) if got[i].tobytes() != exp[i].tobytes()]
+            assert not bad, (sorted_, tail, branches, [(int(off[i]), int(ln[i])) for i in bad[:5]])
+        finally:
+            P.crystal_batch_free(plan)
+
+
 @pytest.mark.parametrize("bad", [dict(block=512), dict(block=96), dict(depth=4),
                                  dict(n_streams=9)])
 def test_batch_plan_rejects_bad_tuning(P, torch_cuda, bad):
