@@ -61,6 +61,28 @@ def test_direct_ragged_jobs(P, torch_cuda):
         assert roots[j].tobytes() == er, j
 
 
+def test_golden_fixtures(P, torch_cuda):
+    """The HIP path against the stored fixtures (tests/golden/): direct
+    hashing of the seeded 1 MiB input and chunking of 1 MiB of the chunking
+    recipe, compared with the stored digests and ends."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_golden as mg
+    data = mg.direct_input()
+    d, n = P.to_device_bytes(data)
+    seg, roots, _, _ = P.direct_device(d, [0], [n])
+    es, er = mg.read_direct()
+    assert [r.tobytes() for r in _np(seg)] == es
+    assert _np(roots)[0].tobytes() == er
+    cdata, base = mg.cdc_input()
+    cd, cn = P.to_device_bytes(cdata)
+    ends, dig = P.cdc_device(cd, cn, P.cdc_params(base))
+    ee, ed = mg.read_cdc()
+    assert _np(ends).astype(np.uint64).tolist() == ee
+    assert [r.tobytes() for r in _np(dig)] == ed
+
+
 def test_direct_root_loader_boundaries(P, torch_cuda):
     """Jobs whose digest arrays (16 bytes per segment) end on each side of
     the root loader's 64-byte block, 128-byte group and 384-byte chunk
