@@ -121,6 +121,64 @@ def test_each_kernel_as_a_job(lib, kind):
     P.crystal_buffer_release(outb)
 
 
+def test_concurrent_submitters(lib):
+    """Four application threads acquire buffers, submit, wait for and release
+    their own jobs at the same time (MD5 direct, SHA-1 direct, chunking, the
+    empty kernel, at varied sizes), while the library's completion threads
+    run their callbacks: every result equals the oracle's and every callback
+    ran exactly once."""
+    import threading
+    P = lib
+    base = gen.cdc_base()
+    kinds = [(P.K_MD5_DIRECT, P.crystal_direct_params(segment_bytes=4096)),
+             (P.K_SHA1_DIRECT, P.crystal_direct_params(segment_bytes=4096)),
+             (P.K_CDC, P.cdc_params(base)),
+             (P.K_NOP, None)]
+    errors, seen = [], []
+    lock = threading.Lock()
+
+    def on_done(task, user):
+        with lock:
+            seen.append(int(task.contents.in_bytes))
+
+    def worker(w):
+        try:
+            for r in range(12):
+                k, params = kinds[(w + r) % 4]
+                n = 1 + (w * 7919 + r * 104729) % 3_000_000
+                data = gen.random_bytes(1000 * w + r, n)
+                t, inb, outb = _submit(P, k, data, params, callback=on_done)
+                assert P.crystal_wait(t) == 0, (w, r)
+                out = P.buffer_view(outb)[:t.out_bytes]
+                if k == P.K_NOP:
+                    assert np.array_equal(out, data), (w, r)
+                elif k == P.K_MD5_DIRECT:
+                    es, er = oracle.direct(data)
+                    assert np.array_equal(out[:-16].reshape(-1, 16), es), (w, r)
+                    assert out[-16:].tobytes() == er, (w, r)
+                elif k == P.K_SHA1_DIRECT:
+                    es, er = oracle.sha1_direct(data)
+                    assert np.array_equal(out[:-20].reshape(-1, 20), es), (w, r)
+                    assert out[-20:].tobytes() == er, (w, r)
+                else:
+                    ends, dig = P.parse_cdc_output(out)
+                    ee, ed = oracle.cdc(data, base)
+                    assert np.array_equal(ends, ee) and np.array_equal(dig, ed), (w, r)
+                P.crystal_buffer_release(inb)
+                P.crystal_buffer_release(outb)
+        except BaseException as e:  # reported by the main thread
+            errors.append((w, e))
+
+    threads = [threading.Thread(target=worker, args=(w,)) for w in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=120)
+    assert not any(th.is_alive() for th in threads)
+    assert not errors, errors[:2]
+    assert len(seen) == 48
+
+
 def test_poll_timeout_and_busy_release(lib):
     P = lib
     data = gen.random_bytes(1, 64 << 20)
