@@ -73,19 +73,29 @@ __device__ __forceinline__ void roll16_store(WT &w, const uint4 &cin, const uint
 }
 
 // MODE 0: candidate bitmap.  MODE 1: dump the 64-bit window hash per byte.
+//
+// 2^lgk consecutive lanes share one 4 KiB range: each rolls its own
+// (4096 >> lgk)-byte part after its own warm-up, and the lanes combine the
+// range's level-2 mask and count with shuffles.  A small input thus fills
+// more of the chip (one lane per range would leave each lane a long serial
+// roll); large inputs use one lane per range.
 template <typename WT, int MODE>
 __global__ __launch_bounds__(256) void k_cdc_roll(const uint8_t *__restrict__ in,
                                                   uint64_t n, uint64_t base, uint64_t b48,
                                                   uint64_t mask, uint64_t *__restrict__ l1,
                                                   uint64_t *__restrict__ l2,
                                                   uint32_t *__restrict__ cnt,
-                                                  uint64_t *__restrict__ wout)
+                                                  uint64_t *__restrict__ wout, uint32_t lgk)
 {
-    const uint64_t L = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t r0 = L * kRangeBytes;
-    if (r0 >= n)
-        return;
-    const uint64_t r1 = (r0 + kRangeBytes < n) ? r0 + kRangeBytes : n;
+    const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t L = lane >> lgk;                        // range
+    const uint32_t sub = (uint32_t)(lane & ((1u << lgk) - 1)); // part of the range
+    const uint64_t part = kRangeBytes >> lgk;              // a multiple of 64 bytes
+    if (L * kRangeBytes >= n)
+        return; // the range's lanes all leave here together
+    const uint64_t r0 = L * kRangeBytes + sub * part;
+    const uint64_t r1 = r0 >= n ? r0 : ((r0 + part < n) ? r0 + part : n);
+    const uint32_t g_base = (uint32_t)(sub * (part >> 6)); // first level-1 word of the part
     const WT B = (WT)base, B48 = (WT)b48, M = (WT)mask;
     const uint4 zero = make_uint4(0, 0, 0, 0);
 
@@ -131,7 +141,7 @@ __global__ __launch_bounds__(256) void k_cdc_roll(const uint8_t *__restrict__ in
                 word &= (r1 - pos >= 64) ? ~0ull : ((1ull << (r1 - pos)) - 1);
             if (word) {
                 l1[pos >> 6] = word;
-                l2bits |= 1ull << g;
+                l2bits |= 1ull << (g_base + g);
                 count += __popcll(word);
             }
         } else {
@@ -149,9 +159,28 @@ __global__ __launch_bounds__(256) void k_cdc_roll(const uint8_t *__restrict__ in
         c3 = n3;
     }
     if (MODE == 0) {
-        l2[L] = l2bits;
-        cnt[L] = count;
+        // the lanes of one range are consecutive within a wave
+        for (uint32_t o = 1; o < (1u << lgk); o <<= 1) {
+            l2bits |= __shfl_xor(l2bits, (int)o);
+            count += __shfl_xor(count, (int)o);
+        }
+        if (sub == 0) {
+            l2[L] = l2bits;
+            cnt[L] = count;
+        }
     }
+}
+
+// Lanes per range (log2) for an input of n_ranges ranges: the most, up to
+// 16, that keep the launch within about one wave per SIMD (256 CUs x 4
+// SIMDs x 64 lanes), beyond which smaller parts only add warm-ups.
+static uint32_t roll_lanes_log2(uint64_t n_ranges)
+{
+    const uint64_t target = 256 * 4 * 64;
+    uint32_t lg = 0;
+    while (lg < 4 && (n_ranges << (lg + 1)) <= target)
+        lg++;
+    return lg;
 }
 
 // ------------------------------------------------------------------ scans
@@ -476,13 +505,14 @@ hipError_t launch_cdc_candidates(const uint8_t *in, const CdcGeom &g, const CdcP
     uint64_t *l1 = reinterpret_cast<uint64_t *>(ws + g.off_l1);
     uint64_t *l2 = reinterpret_cast<uint64_t *>(ws + g.off_l2);
     uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + g.off_cnt);
-    const dim3 grid(nblk(g.n_ranges, 256)), block(256);
+    const uint32_t lgk = roll_lanes_log2(g.n_ranges);
+    const dim3 grid(nblk(g.n_ranges << lgk, 256)), block(256);
     if (p.mask_bits <= 32)
         hipLaunchKernelGGL((k_cdc_roll<uint32_t, 0>), grid, block, 0, s, in, g.n, p.base,
-                           p.b48, p.mask, l1, l2, cnt, (uint64_t *)nullptr);
+                           p.b48, p.mask, l1, l2, cnt, (uint64_t *)nullptr, lgk);
     else
         hipLaunchKernelGGL((k_cdc_roll<uint64_t, 0>), grid, block, 0, s, in, g.n, p.base,
-                           p.b48, p.mask, l1, l2, cnt, (uint64_t *)nullptr);
+                           p.b48, p.mask, l1, l2, cnt, (uint64_t *)nullptr, lgk);
     return hipGetLastError();
 }
 
@@ -581,9 +611,12 @@ hipError_t launch_window_hash(const uint8_t *in, uint64_t n, uint64_t base, uint
     for (int i = 0; i < 48; i++)
         b48 *= base;
     const uint64_t nr = (n + kRangeBytes - 1) / kRangeBytes;
-    hipLaunchKernelGGL((k_cdc_roll<uint64_t, 1>), dim3(nblk(nr, 256)), dim3(256), 0, s, in, n,
-                       base, b48, ~0ull, (uint64_t *)nullptr, (uint64_t *)nullptr,
-                       (uint32_t *)nullptr, w);
+    // the same split of ranges into parts as the candidate launch, so the
+    // full-hash dump checks every part's warm-up
+    const uint32_t lgk = roll_lanes_log2(nr);
+    hipLaunchKernelGGL((k_cdc_roll<uint64_t, 1>), dim3(nblk(nr << lgk, 256)), dim3(256), 0, s,
+                       in, n, base, b48, ~0ull, (uint64_t *)nullptr, (uint64_t *)nullptr,
+                       (uint32_t *)nullptr, w, lgk);
     return hipGetLastError();
 }
 

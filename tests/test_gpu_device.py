@@ -272,6 +272,31 @@ def test_candidates_vs_oracle(P, torch_cuda, case):
     assert np.array_equal(got, oracle.candidates(data, base, bits))
 
 
+# inputs whose range counts give the candidate launch 8, 4 and 2 lanes per
+# 4 KiB range (the other tests cover 16 lanes, small inputs, and 1 lane,
+# the 256 MiB input)
+@pytest.mark.parametrize("n", [20 * (1 << 20) + 5, 50 * (1 << 20) + 1, 100 * (1 << 20) + 3],
+                         ids=["8_lanes", "4_lanes", "2_lanes"])
+def test_candidates_every_lane_split(P, torch_cuda, n):
+    base = gen.cdc_base()
+    data = gen.random_bytes(n & 0xFFFF, n)
+    params = P.cdc_params(base, mask_bits=10)
+    *_, got = _candidates(P, torch_cuda, data, params)
+    assert np.array_equal(got, oracle.candidates(data, base, 10))
+
+
+def test_window_hash_8_lanes_per_range(P, torch_cuda):
+    """The full 64-bit window hash at every byte of a 20 MiB input, rolled
+    by 8 lanes per 4 KiB range (512-byte parts, each after its own warm-up)."""
+    torch = torch_cuda
+    base = gen.cdc_base()
+    data = gen.random_bytes(4321, 20 * (1 << 20) + 9)
+    d, n = P.to_device_bytes(data)
+    w = torch.empty(n, dtype=torch.int64, device="cuda")
+    P.crystal_window_hash_device(d, n, base, w)
+    assert np.array_equal(_np(w).view(np.uint64), oracle.window_hash(data, base))
+
+
 SELECT_CASES = {
     # name: (data builder, base, min, max, mask_bits)
     "c3_like_16mib": (lambda: gen.cdc_input(n_blocks=256, seed=3), None, 2048, 65536, 13),
