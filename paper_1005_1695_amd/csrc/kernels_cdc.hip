@@ -14,8 +14,9 @@
 // 2. Selection (the chunk rule is a sequential chain: each chunk start fixes
 //    the next).  The input is split into tiles of P >= max_len bytes.  Each
 //    tile's lane walks the chain speculatively from D bytes before its tile
-//    (D = 2P), records the starts that fall inside its tile and the first
-//    start past it (its exit).  Two chains that reach the same start agree
+//    (D = 2P; inputs of up to 256 tiles use about two mean chunk lengths,
+//    at least 16 KiB), records the starts that fall inside its tile and the
+//    first start past it (its exit).  Two chains that reach the same start agree
 //    from then on, so if the exit of tile t-1 equals the first start tile t
 //    recorded, tile t's starts are exact; tile 0 starts at 0 and is exact.
 //    A verification pass checks every tile in parallel; tiles that fail are
@@ -342,14 +343,124 @@ __device__ uint64_t walk_tile(const SelArgs &a, uint32_t t, uint64_t s)
     return s;
 }
 
+// Inclusive scan of x over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x, uint32_t lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= (uint32_t)d)
+            x += y;
+    }
+    return x;
+}
+
+// Candidates (and level-1 words holding them) one tile's span may keep in LDS.
+constexpr uint32_t kSelCap = 2048;
+
+// One wave per tile.  A lone lane walking the chain through the bitmaps pays
+// two or three dependent global loads per chunk.  Instead the wave first
+// gathers, in LDS and in position order, every candidate the walk can look
+// at: the span from its speculative start s0 to the last position its final
+// step can reach (tile end - 1 + max_len).  Lanes read the span's level-2
+// words in parallel, list the set bits (the nonzero level-1 words), read
+// those in parallel and expand them into positions, relative to the span's
+// first range.  Lane 0 then walks the chain in LDS, keeping a cursor into
+// the sorted list (chunk starts only increase, so it never moves back).  A
+// span with more than kSelCap candidates, or wider than 4 GiB, is walked
+// through global memory as before.
 __global__ __launch_bounds__(64) void k_sel_walk(SelArgs a)
 {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint32_t words[kSelCap]; // level-1 word index - R0 * 64
+    __shared__ uint32_t cand[kSelCap];  // candidate position - R0 * 4096
+    const uint32_t t = blockIdx.x;
+    const uint32_t lane = threadIdx.x;
     if (t >= a.n_tiles)
         return;
     const uint64_t lt = (uint64_t)t * a.tile_bytes;
-    const uint64_t s = lt > a.warm_bytes ? lt - a.warm_bytes : 0;
-    walk_tile(a, t, s);
+    const uint64_t lt1 = a.n - lt < a.tile_bytes ? a.n : lt + a.tile_bytes;
+    const uint64_t s0 = lt > a.warm_bytes ? lt - a.warm_bytes : 0;
+    const uint64_t e = a.n - lt1 < a.max_len ? a.n : lt1 + a.max_len;
+    const uint64_t R0 = s0 / kRangeBytes, R1 = (e - 1) / kRangeBytes;
+    const uint64_t base = R0 * kRangeBytes;
+    bool fits = (R1 + 1 - R0) * kRangeBytes <= (1ull << 32);
+    uint32_t nw = 0, nc = 0;
+    for (uint64_t Rb = R0; fits && Rb <= R1; Rb += 64) {
+        const uint64_t R = Rb + lane;
+        uint64_t m = R <= R1 ? a.l2[R] : 0;
+        const uint32_t k = (uint32_t)__popcll(m);
+        const uint32_t x = wave_scan_incl(k, lane);
+        const uint32_t tot = __shfl(x, 63, 64);
+        if (nw + tot > kSelCap) {
+            fits = false;
+            break;
+        }
+        uint32_t o = nw + x - k;
+        const uint32_t w0 = (uint32_t)((R - R0) << 6);
+        while (m) {
+            words[o++] = w0 + (uint32_t)__builtin_ctzll(m);
+            m &= m - 1;
+        }
+        nw += tot;
+    }
+    __syncthreads();
+    for (uint32_t wb = 0; fits && wb < nw; wb += 64) {
+        const uint32_t i = wb + lane;
+        uint32_t wi = 0;
+        uint64_t bits = 0;
+        if (i < nw) {
+            wi = words[i];
+            bits = a.l1[(R0 << 6) + wi];
+        }
+        const uint32_t k = (uint32_t)__popcll(bits);
+        const uint32_t x = wave_scan_incl(k, lane);
+        const uint32_t tot = __shfl(x, 63, 64);
+        if (nc + tot > kSelCap) {
+            fits = false;
+            break;
+        }
+        uint32_t o = nc + x - k;
+        while (bits) {
+            cand[o++] = (wi << 6) + (uint32_t)__builtin_ctzll(bits);
+            bits &= bits - 1;
+        }
+        nc += tot;
+    }
+    __syncthreads();
+    if (lane != 0)
+        return;
+    if (!fits) {
+        walk_tile(a, t, s0);
+        return;
+    }
+    uint32_t c = 0, p = 0;
+    uint64_t first = kNone, s = s0;
+    uint64_t *dst = a.starts + (uint64_t)t * a.tile_cap;
+    while (s < lt1) {
+        if (s >= lt) {
+            if (c < a.tile_cap)
+                dst[c] = s;
+            else
+                a.bad[1] = 1;
+            if (c == 0)
+                first = s;
+            c++;
+        }
+        // the chunk's end: first candidate in [s + min - 1, min(s + max - 1, n - 1)]
+        const uint64_t lo = s + a.min_len - 1;
+        uint64_t hi = s + a.max_len - 1;
+        if (hi > a.n - 1)
+            hi = a.n - 1;
+        while (p < nc && base + cand[p] < lo)
+            p++;
+        if (p < nc && base + cand[p] <= hi)
+            s = base + cand[p] + 1;
+        else
+            s = s + a.max_len <= a.n ? s + a.max_len : a.n;
+    }
+    a.first[t] = (c ? first : s);
+    a.tcnt[t] = c;
+    a.exit_[t] = s;
 }
 
 __global__ __launch_bounds__(256) void k_sel_verify(SelArgs a)
@@ -566,7 +677,7 @@ hipError_t launch_cdc_select(const CdcGeom &g, const CdcParams &p, uint8_t *ws,
     e = launch_zero_u32(a.bad, 2u, s);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_sel_walk, dim3(nblk(g.n_tiles, 64)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_sel_walk, dim3(g.n_tiles), dim3(64), 0, s, a);
     hipLaunchKernelGGL(k_sel_verify, dim3(nblk(g.n_tiles, 256)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_sel_repair, dim3(1), dim3(64), 0, s, a);
     hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, a.tcnt, (uint64_t)g.n_tiles,

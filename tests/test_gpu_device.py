@@ -309,6 +309,15 @@ SELECT_CASES = {
     "min_one": (lambda: gen.random_bytes(13, 200_000), None, 1, 64, 3),
     "short": (lambda: gen.random_bytes(14, 3000), None, 2048, 65536, 13),
     "exact_max": (lambda: gen.random_bytes(15, 65536), None, 2048, 65536, 64),
+    # zero bytes make every position a candidate: tiles whose span reaches
+    # them hold too many for LDS and walk through global memory, the others
+    # walk from LDS
+    "zeros_then_random": (lambda: np.concatenate([np.zeros(1 << 20, np.uint8),
+                                                  gen.random_bytes(16, 3_000_001)]),
+                          None, 2048, 65536, 13),
+    # 272 tiles: past the short warm-up, each tile walks 2P before its start
+    "tiles_272_long_warm": (lambda: gen.random_bytes(17, 17 * (1 << 20) + 5), None, 2048,
+                            65536, 13),
 }
 
 
