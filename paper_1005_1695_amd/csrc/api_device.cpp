@@ -402,30 +402,31 @@ int crystal_cdc_device(const void *d_in, uint64_t n, const crystal_cdc_params *p
                        size_t ws_bytes, uint64_t *d_n_chunks, uint64_t *d_ends,
                        void *d_digests, uint64_t cap, void *stream)
 {
-    int rc = crystal_cdc_candidates_device(d_in, n, p, d_ws, ws_bytes, nullptr, nullptr, 0,
-                                           stream);
-    if (rc)
-        return rc;
-    rc = crystal_cdc_select_device(n, p, d_ws, ws_bytes, d_n_chunks, d_ends, cap, stream);
-    if (rc)
-        return rc;
-    if (cap == 0)
-        return CRYSTAL_OK;
-    if (!d_digests)
-        return fail(CRYSTAL_EINVAL, "null pointer argument");
     CdcParams cp;
     CdcGeom g;
-    rc = cdc_prepare(n, p, ws_bytes, &cp, &g); // validated by the steps above
+    int rc = cdc_prepare(n, p, ws_bytes, &cp, &g);
     if (rc)
         return rc;
-    const uint32_t *order = nullptr;
-    hipError_t e = launch_chunk_order(g, (uint8_t *)d_ws, d_n_chunks, d_ends, cap, &order,
-                                      (hipStream_t)stream);
-    if (e == hipSuccess)
-        e = launch_md5_chunks((const uint8_t *)d_in, d_ends, d_n_chunks, cap, order,
-                              (uint8_t *)d_digests, (hipStream_t)stream);
+    if (!d_n_chunks || (n && (!d_in || !d_ws || !d_ends)) || (cap && !d_digests))
+        return fail(CRYSTAL_EINVAL, "null pointer argument");
+    if (cap < cdc_max_chunks(n, cp))
+        return fail(CRYSTAL_EINVAL, "cap %llu < crystal_cdc_max_chunks %llu",
+                    (unsigned long long)cap, (unsigned long long)cdc_max_chunks(n, cp));
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_cdc_candidates((const uint8_t *)d_in, g, cp, (uint8_t *)d_ws, s);
     if (e != hipSuccess)
-        return hip_fail(e, "chunk order / md5_chunks launch");
+        return hip_fail(e, "cdc_candidates launch");
+    const uint32_t *order = nullptr;
+    e = launch_cdc_select(g, cp, (uint8_t *)d_ws, d_n_chunks, d_ends, cap, s,
+                          cap ? &order : nullptr);
+    if (e != hipSuccess)
+        return hip_fail(e, "cdc_select launch");
+    if (cap == 0)
+        return CRYSTAL_OK;
+    e = launch_md5_chunks((const uint8_t *)d_in, d_ends, d_n_chunks, cap, order,
+                          (uint8_t *)d_digests, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "md5_chunks launch");
     return CRYSTAL_OK;
 }
 

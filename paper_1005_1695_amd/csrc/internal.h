@@ -102,9 +102,11 @@ hipError_t launch_cdc_candidates(const uint8_t *in, const CdcGeom &g,
                                  const CdcParams &p, uint8_t *ws, hipStream_t s);
 hipError_t launch_cdc_compact(const CdcGeom &g, uint8_t *ws, uint64_t *d_count,
                               uint64_t *d_cand, uint64_t cap, hipStream_t s);
+// Chunk ends from the candidate bitmap.  With `order` non-null it also makes
+// the chunk order (as launch_chunk_order does) and returns it in *order.
 hipError_t launch_cdc_select(const CdcGeom &g, const CdcParams &p, uint8_t *ws,
                              uint64_t *d_n_chunks, uint64_t *d_ends,
-                             uint64_t cap, hipStream_t s);
+                             uint64_t cap, hipStream_t s, const uint32_t **order = nullptr);
 // Chunk order for the digest launch: chunk indices grouped into 1 KiB length
 // classes, longest class first (order inside a class unspecified).  Writes
 // ws + g.off_ord and returns that pointer in *order.

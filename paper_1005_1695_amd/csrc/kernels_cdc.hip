@@ -13,15 +13,17 @@
 //
 // 2. Selection (the chunk rule is a sequential chain: each chunk start fixes
 //    the next).  The input is split into tiles of P >= max_len bytes.  Each
-//    tile's lane walks the chain speculatively from D bytes before its tile
-//    (D = 2P; inputs of up to 256 tiles use about two mean chunk lengths,
-//    at least 16 KiB), records the starts that fall inside its tile and the
-//    first start past it (its exit).  Two chains that reach the same start agree
+//    tile walks the chain speculatively from D bytes before its tile (D = 2P;
+//    inputs of up to 256 tiles use about two mean chunk lengths, at least
+//    16 KiB), records the starts that fall inside its tile and the first
+//    start past it (its exit).  Two chains that reach the same start agree
 //    from then on, so if the exit of tile t-1 equals the first start tile t
 //    recorded, tile t's starts are exact; tile 0 starts at 0 and is exact.
 //    A verification pass checks every tile in parallel; tiles that fail are
 //    re-walked from the true entry by a repair pass (rare on real data).
 //    A scan of per-tile counts then packs the starts into the ends array.
+//    Inputs of up to 1024 tiles do all of this after the walk, and the
+//    chunk order, in one workgroup.
 #include "internal.h"
 
 namespace crystal {
@@ -606,6 +608,85 @@ __global__ __launch_bounds__(256) void k_chunk_scatter(const uint64_t *__restric
         order[base[cls] + local] = (uint32_t)k;
 }
 
+// ------------------------------------------------------- one-launch finish
+// For an input of up to kFinishTiles tiles, one workgroup does what follows
+// the walk: verification, the serial repair, the scan of the tiles' counts,
+// the packing of the ends and, when `order` is given, the length-class
+// counting sort of the chunks.  A small chunking job then issues three
+// launches (candidates, walk, finish) instead of eleven, each of which would
+// cost a few microseconds of serial time.
+constexpr uint32_t kFinishTiles = 1024;     // one thread per tile
+constexpr uint64_t kFinishOrderCap = 65536; // chunks the workgroup orders
+
+__global__ __launch_bounds__(1024) void k_sel_finish(SelArgs a, uint64_t *__restrict__ n_chunks,
+                                                     uint64_t *__restrict__ ends, uint64_t cap,
+                                                     uint32_t *__restrict__ order, uint64_t ocap)
+{
+    __shared__ uint32_t s_bad;
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t cls_n[kLenClasses];
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t == 0)
+        s_bad = 0;
+    if (t < kLenClasses)
+        cls_n[t] = 0;
+    __syncthreads();
+    if (t >= 1 && t < a.n_tiles && a.exit_[t - 1] != a.first[t])
+        atomicAdd(&s_bad, 1u);
+    __syncthreads();
+    if (s_bad) {
+        if (t == 0) {
+            for (uint32_t u = 1; u < a.n_tiles; u++) {
+                const uint64_t entry = a.exit_[u - 1];
+                if (entry != a.first[u])
+                    walk_tile(a, u, entry);
+            }
+        }
+        __syncthreads();
+    }
+    // exclusive scan of the tiles' start counts (the input is below 2^31
+    // bytes, so the total fits 32 bits)
+    const uint32_t c = t < a.n_tiles ? a.tcnt[t] : 0;
+    const uint32_t x = wave_scan_incl(c, lane);
+    if (lane == 63)
+        wsum[wv] = x;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (uint32_t k = 0; k < 16; k++) {
+        before += k < wv ? wsum[k] : 0;
+        total += wsum[k];
+    }
+    // start number j >= 1 is end j-1; the last end is n
+    const uint64_t o = before + x - c;
+    const uint64_t *src = a.starts + (uint64_t)t * a.tile_cap;
+    for (uint32_t i = 0; i < c; i++) {
+        const uint64_t k = o + i;
+        if (k >= 1 && k - 1 < cap)
+            ends[k - 1] = src[i];
+    }
+    const uint64_t m = total;
+    if (t == 0) {
+        if (m >= 1 && m - 1 < cap)
+            ends[m - 1] = a.n;
+        *n_chunks = m;
+    }
+    if (order == nullptr)
+        return;
+    __syncthreads(); // the ends above are visible to the whole workgroup
+    const uint64_t nc = m < ocap ? m : ocap;
+    for (uint64_t k = t; k < nc; k += 1024)
+        atomicAdd(&cls_n[len_class(chunk_len(ends, k))], 1u);
+    __syncthreads();
+    if (wv == 0) {
+        const uint32_t v = cls_n[lane];
+        const uint32_t y = wave_scan_incl(v, lane);
+        cls_n[lane] = y - v; // first slot of the class
+    }
+    __syncthreads();
+    for (uint64_t k = t; k < nc; k += 1024)
+        order[atomicAdd(&cls_n[len_class(chunk_len(ends, k))], 1u)] = (uint32_t)k;
+}
+
 static inline uint32_t nblk(uint64_t n, uint32_t b) { return (uint32_t)((n + b - 1) / b); }
 
 hipError_t launch_cdc_candidates(const uint8_t *in, const CdcGeom &g, const CdcParams &p,
@@ -649,8 +730,10 @@ hipError_t launch_cdc_compact(const CdcGeom &g, uint8_t *ws, uint64_t *d_count,
 
 hipError_t launch_cdc_select(const CdcGeom &g, const CdcParams &p, uint8_t *ws,
                              uint64_t *d_n_chunks, uint64_t *d_ends, uint64_t cap,
-                             hipStream_t s)
+                             hipStream_t s, const uint32_t **order)
 {
+    if (order)
+        *order = nullptr;
     if (g.n == 0) {
         hipLaunchKernelGGL(k_store_zero_u64, dim3(1), dim3(64), 0, s, d_n_chunks);
         return hipGetLastError();
@@ -674,6 +757,24 @@ hipError_t launch_cdc_select(const CdcGeom &g, const CdcParams &p, uint8_t *ws,
     uint64_t *toff = reinterpret_cast<uint64_t *>(ws + g.off_toff);
     uint64_t *total = reinterpret_cast<uint64_t *>(ws + g.off_misc);
     hipError_t e;
+    if (g.n_tiles <= kFinishTiles && g.n < (1ull << 31)) {
+        // the finisher orders the chunks too when they are few enough
+        const uint64_t ocap = cap < g.ord_cap ? cap : g.ord_cap;
+        uint32_t *ord = nullptr;
+        if (order && ocap > 0 && ocap <= kFinishOrderCap)
+            ord = reinterpret_cast<uint32_t *>(ws + g.off_ord);
+        hipLaunchKernelGGL(k_sel_walk, dim3(g.n_tiles), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(1024), 0, s, a, d_n_chunks, d_ends, cap,
+                           ord, ocap);
+        e = hipGetLastError();
+        if (e != hipSuccess || !order)
+            return e;
+        if (ord) {
+            *order = ord;
+            return hipSuccess;
+        }
+        return launch_chunk_order(g, ws, d_n_chunks, d_ends, cap, order, s);
+    }
     e = launch_zero_u32(a.bad, 2u, s);
     if (e != hipSuccess)
         return e;
@@ -685,7 +786,9 @@ hipError_t launch_cdc_select(const CdcGeom &g, const CdcParams &p, uint8_t *ws,
     hipLaunchKernelGGL(k_sel_emit, dim3(nblk(g.n_tiles, 64)), dim3(64), 0, s, a, toff, total,
                        d_n_chunks, d_ends, cap);
     e = hipGetLastError();
-    return e;
+    if (e != hipSuccess || !order)
+        return e;
+    return launch_chunk_order(g, ws, d_n_chunks, d_ends, cap, order, s);
 }
 
 hipError_t launch_chunk_order(const CdcGeom &g, uint8_t *ws, const uint64_t *d_n_chunks,

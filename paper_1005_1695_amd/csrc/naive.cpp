@@ -79,11 +79,9 @@ extern "C" int crystal_naive_run(int kernel_id, const void *params, const void *
         case CRYSTAL_K_CDC: {
             uint64_t *cnt = reinterpret_cast<uint64_t *>(d_out);
             e = launch_cdc_candidates(d_in, g, cp, d_ws, s);
-            if (e == hipSuccess)
-                e = launch_cdc_select(g, cp, d_ws, cnt, cnt + 1, cap, s);
             const uint32_t *order = nullptr;
             if (e == hipSuccess)
-                e = launch_chunk_order(g, d_ws, cnt, cnt + 1, cap, &order, s);
+                e = launch_cdc_select(g, cp, d_ws, cnt, cnt + 1, cap, s, &order);
             if (e == hipSuccess)
                 e = launch_md5_chunks(d_in, cnt + 1, cnt, cap, order, nullptr, s);
             break;

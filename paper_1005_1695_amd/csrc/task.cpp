@@ -408,11 +408,9 @@ static hipError_t enqueue_batch(Lib *L, Batch *b)
             uint64_t *cnt = reinterpret_cast<uint64_t *>(d_out);
             uint64_t *ends = cnt + 1;
             e = launch_cdc_candidates(d_in, j->g, j->cp, d_ws, st);
-            if (e == hipSuccess)
-                e = launch_cdc_select(j->g, j->cp, d_ws, cnt, ends, j->cap, st);
             const uint32_t *order = nullptr;
             if (e == hipSuccess)
-                e = launch_chunk_order(j->g, d_ws, cnt, ends, j->cap, &order, st);
+                e = launch_cdc_select(j->g, j->cp, d_ws, cnt, ends, j->cap, st, &order);
             const bool chained = std::find(cdc.begin(), cdc.end(), j) != cdc.end();
             if (e == hipSuccess && !chained)
                 e = launch_md5_chunks(d_in, ends, cnt, j->cap, order, nullptr, st);

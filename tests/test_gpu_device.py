@@ -355,6 +355,20 @@ def test_cdc_empty(P, torch_cuda):
     assert e.numel() == 0 and dg.shape[0] == 0
 
 
+def test_select_over_1024_tiles_with_repairs(P, torch_cuda):
+    """1041 tiles, past what one finishing workgroup takes: zero bytes with a
+    3000-byte minimum put nearly every speculative tile chain out of phase,
+    so the multi-kernel path verifies and repairs them (smaller inputs repair
+    inside the one-workgroup finish: the zeros_repair case)."""
+    base = gen.cdc_base()
+    data = np.zeros(65 * (1 << 20) + 123, np.uint8)
+    d, n = P.to_device_bytes(data)
+    e, dg = P.cdc_device(d, n, P.cdc_params(base, 3000, 65536, 13))
+    exp_e, exp_d = oracle.cdc(data, base, 13, 3000, 65536)
+    assert np.array_equal(_np(e).view(np.uint64), exp_e)
+    assert np.array_equal(_np(dg), exp_d)
+
+
 def test_cdc_full_size_256mib(P, torch_cuda):
     """The chunking workload at full size (256 MiB, 20 % repeated blocks)."""
     torch = torch_cuda
