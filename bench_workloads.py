@@ -457,14 +457,15 @@ def chunking(P, torch, gen, reps=10):
 
 # --------------------------------------------------------------------- serving
 
-def serving(P, torch, gen, loads, n_jobs, n_streams=3):
+def serving(P, torch, gen, loads, n_jobs, n_streams=3, direct_frac=0.7):
     arena_bytes = 4 << 30
     arena = torch.empty(arena_bytes, dtype=torch.uint8).pin_memory()
     gen.fill(gen.sub_seed(gen.config_seed(4), 5), arena.data_ptr(), arena_bytes)
     base = gen.cdc_base()
     cdcp = P.cdc_params(base)
     direct = P.crystal_direct_params(segment_bytes=4096)
-    spec0 = gen.serving_jobs(n_jobs=n_jobs, load_gbps=1.0, arena_bytes=arena_bytes)
+    spec0 = gen.serving_jobs(n_jobs=n_jobs, load_gbps=1.0, arena_bytes=arena_bytes,
+                             direct_frac=direct_frac)
     caps = np.array([P.crystal_output_bytes(P.K_CDC if k else P.K_MD5_DIRECT, int(sz),
                                             cdcp if k else direct)
                      for sz, k in zip(spec0["size"], spec0["kind"])], dtype=np.int64)
@@ -476,7 +477,8 @@ def serving(P, torch, gen, loads, n_jobs, n_streams=3):
     results = []
     try:
         for load in loads:
-            spec = gen.serving_jobs(n_jobs=n_jobs, load_gbps=load, arena_bytes=arena_bytes)
+            spec = gen.serving_jobs(n_jobs=n_jobs, load_gbps=load, arena_bytes=arena_bytes,
+                                    direct_frac=direct_frac)
             jobs = (P.crystal_drive_job * n_jobs)()
             for k in range(n_jobs):
                 kid = P.K_CDC if spec["kind"][k] else P.K_MD5_DIRECT
@@ -511,6 +513,7 @@ def serving(P, torch, gen, loads, n_jobs, n_streams=3):
     op = max(ok_pts, key=lambda r: r["offered_gbps"]) if ok_pts else None
     return out("serving", {"points": results, "operating_point": op,
                            "mean_job_bytes": float(spec0["size"].mean()),
+                           "direct_frac": direct_frac,
                            "device_pool_gib": 16, "compute_streams": n_streams})
 
 
@@ -587,6 +590,8 @@ def main() -> int:
     ap.add_argument("--loads", default="5,10,20,30,40,45,50")
     ap.add_argument("--serving-jobs", type=int, default=0)
     ap.add_argument("--serving-streams", type=int, default=3)
+    ap.add_argument("--serving-direct-frac", type=float, default=0.7,
+                    help="share of direct-hashing jobs in the serving mix (the rest chunk)")
     ap.add_argument("--batch-buffers", type=int, default=0)
     ap.add_argument("--sha1-streams", type=int, default=3)
     ap.add_argument("--sha1-window", type=int, default=24)
@@ -637,7 +642,7 @@ def main() -> int:
     if want("serving"):
         loads = [float(x) for x in args.loads.split(",")]
         serving(P, torch, gen, loads, args.serving_jobs or (2000 if args.quick else 20000),
-                args.serving_streams)
+                args.serving_streams, args.serving_direct_frac)
     return 0
 
 

@@ -75,6 +75,166 @@ __device__ __forceinline__ void roll16_store(WT &w, const uint4 &cin, const uint
     }
 }
 
+// ------------------------------------------ two parts per lane, 16-bit halves
+// A mask of at most 15 bits reads only W mod 2^16, and W mod 2^16 rolls
+// exactly in 16-bit arithmetic (reduction mod 2^16 is a ring homomorphism).
+// So each lane rolls two parts at once, one in each 16-bit half of a
+// register, with packed multiply-adds (v_pk_mad_u16): about 4.5 VALU
+// instructions per byte against about 9 for the 32-bit roll, and no 32-bit
+// multiplies.  The candidate test needs no compare either: for M < 2^15,
+// (W & M) - 1 taken in 16 bits has its top bit set exactly when W & M == 0.
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t vword(const uint4 &v, int t)
+{
+    return (t < 4) ? v.x : (t < 8) ? v.y : (t < 12) ? v.z : v.w;
+}
+
+// Byte t of a in the low half, byte t of b in the high half.  The permute
+// selector picks from the 8 bytes {b word (4..7), a word (0..3)}; 0x0c
+// yields a zero byte.
+__device__ __forceinline__ u16x2 pair_bytes(const uint4 &a, const uint4 &b, int t)
+{
+    const uint32_t sel = 0x0c000c00u | ((4u + (uint32_t)(t & 3)) << 16) | (uint32_t)(t & 3);
+    return __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(vword(b, t), vword(a, t), sel));
+}
+
+// Roll 16 positions of both parts.  Bit t of the result flags part A's
+// position t, bit 16 + t part B's: each step shifts the flags right by one
+// and adds the new ones at bits 15 and 31, so that after 16 steps step t's
+// flags sit at t and 16 + t without crossing between the halves.
+__device__ __forceinline__ uint32_t roll16x2(u16x2 &w, const uint4 &ia, const uint4 &ib,
+                                             const uint4 &oa, const uint4 &ob, u16x2 B,
+                                             u16x2 nB48, uint32_t M2)
+{
+    const u16x2 one = {1, 1};
+    uint32_t bits = 0;
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+        w = w * B + pair_bytes(ia, ib, t);
+        w = pair_bytes(oa, ob, t) * nB48 + w; // - out * B^48
+        const u16x2 z = __builtin_bit_cast(u16x2, __builtin_bit_cast(uint32_t, w) & M2);
+        const uint32_t f = __builtin_bit_cast(uint32_t, (u16x2)(z - one));
+        bits = (bits >> 1) | (f & 0x80008000u);
+    }
+    return bits;
+}
+
+// Candidate bitmap for masks of at most 15 bits.  2^lgk consecutive lanes
+// share a 4 KiB range; lane `sub` rolls its parts 2 sub and 2 sub + 1 of
+// 4096 >> (lgk + 1) bytes, each after its own 48-byte warm-up, so the launch
+// shape and the bytes per lane are those of k_cdc_roll.
+__global__ __launch_bounds__(256) void k_cdc_roll_x2(const uint8_t *__restrict__ in, uint64_t n,
+                                                     uint32_t b16, uint32_t nb48_16, uint32_t M2,
+                                                     uint64_t *__restrict__ l1,
+                                                     uint64_t *__restrict__ l2,
+                                                     uint32_t *__restrict__ cnt, uint32_t lgk)
+{
+    const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t L = lane >> lgk;
+    const uint32_t sub = (uint32_t)(lane & ((1u << lgk) - 1));
+    const uint64_t part = kRangeBytes >> (lgk + 1); // a multiple of 64 bytes, >= 128
+    if (L * kRangeBytes >= n)
+        return; // the range's lanes all leave here together
+    const uint64_t a0 = L * kRangeBytes + 2ull * sub * part, b0 = a0 + part;
+    const uint64_t a1 = a0 >= n ? a0 : ((a0 + part < n) ? a0 + part : n);
+    const uint64_t b1 = b0 >= n ? b0 : ((b0 + part < n) ? b0 + part : n);
+    const uint32_t ga = (uint32_t)(2ull * sub * (part >> 6)); // first level-1 word of part A
+    const uint32_t gb = ga + (uint32_t)(part >> 6);
+    const u16x2 B = __builtin_bit_cast(u16x2, b16 | (b16 << 16));
+    const u16x2 nB48 = __builtin_bit_cast(u16x2, nb48_16 | (nb48_16 << 16));
+    const uint4 zero = make_uint4(0, 0, 0, 0);
+
+    // Warm-up over the 48 bytes before each part (part A of the input's
+    // first lane has none: its half stays 0, as after rolling in zeros).
+    u16x2 w = {0, 0};
+    uint4 pa1 = zero, pa2 = zero, pa3 = zero;
+    if (a0 >= 48) {
+        pa1 = load_vec(in, a0 - 48, n);
+        pa2 = load_vec(in, a0 - 32, n);
+        pa3 = load_vec(in, a0 - 16, n);
+    }
+    uint4 pb1 = load_vec(in, b0 - 48, n), pb2 = load_vec(in, b0 - 32, n),
+          pb3 = load_vec(in, b0 - 16, n);
+    roll16x2(w, pa1, pb1, zero, zero, B, nB48, M2);
+    roll16x2(w, pa2, pb2, zero, zero, B, nB48, M2);
+    roll16x2(w, pa3, pb3, zero, zero, B, nB48, M2);
+
+    uint64_t l2bits = 0;
+    uint32_t count = 0;
+    const uint32_t ngroups = (uint32_t)((a1 - a0 + 63) >> 6); // part B is never longer
+    uint4 ca0 = load_vec(in, a0, n), ca1 = load_vec(in, a0 + 16, n);
+    uint4 ca2 = load_vec(in, a0 + 32, n), ca3 = load_vec(in, a0 + 48, n);
+    uint4 cb0 = load_vec(in, b0, n), cb1 = load_vec(in, b0 + 16, n);
+    uint4 cb2 = load_vec(in, b0 + 32, n), cb3 = load_vec(in, b0 + 48, n);
+    for (uint32_t g = 0; g < ngroups; g++) {
+        const uint64_t pa = a0 + 64ull * g, pb = b0 + 64ull * g;
+        uint4 na0 = zero, na1 = zero, na2 = zero, na3 = zero;
+        uint4 nb0 = zero, nb1 = zero, nb2 = zero, nb3 = zero;
+        if (g + 1 < ngroups) {
+            na0 = load_vec(in, pa + 64, n);
+            na1 = load_vec(in, pa + 80, n);
+            na2 = load_vec(in, pa + 96, n);
+            na3 = load_vec(in, pa + 112, n);
+            nb0 = load_vec(in, pb + 64, n);
+            nb1 = load_vec(in, pb + 80, n);
+            nb2 = load_vec(in, pb + 96, n);
+            nb3 = load_vec(in, pb + 112, n);
+        }
+        // leaving bytes of vector q are those of the vector 48 bytes back
+        const uint32_t r0 = roll16x2(w, ca0, cb0, pa1, pb1, B, nB48, M2);
+        const uint32_t r1 = roll16x2(w, ca1, cb1, pa2, pb2, B, nB48, M2);
+        const uint32_t r2 = roll16x2(w, ca2, cb2, pa3, pb3, B, nB48, M2);
+        const uint32_t r3 = roll16x2(w, ca3, cb3, ca0, cb0, B, nB48, M2);
+        uint64_t wa = (uint64_t)((r0 & 0xffffu) | (r1 << 16)) |
+                      ((uint64_t)((r2 & 0xffffu) | (r3 << 16)) << 32);
+        uint64_t wb = (uint64_t)((r0 >> 16) | (r1 & 0xffff0000u)) |
+                      ((uint64_t)((r2 >> 16) | (r3 & 0xffff0000u)) << 32);
+        // positions below 47 have no full window; positions past a part's
+        // end are outside it (part B may end first, or be empty)
+        if (pa < 47)
+            wa &= ~0ull << (47 - pa);
+        if (pa + 64 > a1)
+            wa &= (1ull << (a1 - pa)) - 1; // pa < a1 here
+        if (pb >= b1)
+            wb = 0;
+        else if (pb + 64 > b1)
+            wb &= (1ull << (b1 - pb)) - 1;
+        if (wa) {
+            l1[pa >> 6] = wa;
+            l2bits |= 1ull << (ga + g);
+            count += __popcll(wa);
+        }
+        if (wb) {
+            l1[pb >> 6] = wb;
+            l2bits |= 1ull << (gb + g);
+            count += __popcll(wb);
+        }
+        pa1 = ca1;
+        pa2 = ca2;
+        pa3 = ca3;
+        ca0 = na0;
+        ca1 = na1;
+        ca2 = na2;
+        ca3 = na3;
+        pb1 = cb1;
+        pb2 = cb2;
+        pb3 = cb3;
+        cb0 = nb0;
+        cb1 = nb1;
+        cb2 = nb2;
+        cb3 = nb3;
+    }
+    for (uint32_t o = 1; o < (1u << lgk); o <<= 1) {
+        l2bits |= __shfl_xor(l2bits, (int)o);
+        count += __shfl_xor(count, (int)o);
+    }
+    if (sub == 0) {
+        l2[L] = l2bits;
+        cnt[L] = count;
+    }
+}
+
 // MODE 0: candidate bitmap.  MODE 1: dump the 64-bit window hash per byte.
 //
 // 2^lgk consecutive lanes share one 4 KiB range: each rolls its own
@@ -699,7 +859,13 @@ hipError_t launch_cdc_candidates(const uint8_t *in, const CdcGeom &g, const CdcP
     uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + g.off_cnt);
     const uint32_t lgk = roll_lanes_log2(g.n_ranges);
     const dim3 grid(nblk(g.n_ranges << lgk, 256)), block(256);
-    if (p.mask_bits <= 32)
+    if (p.mask_bits <= 15) {
+        const uint32_t b16 = (uint32_t)(p.base & 0xffffu);
+        const uint32_t nb48 = (uint32_t)((0ull - p.b48) & 0xffffu);
+        const uint32_t m = (uint32_t)(p.mask & 0xffffu);
+        hipLaunchKernelGGL(k_cdc_roll_x2, grid, block, 0, s, in, g.n, b16, nb48,
+                           m | (m << 16), l1, l2, cnt, lgk);
+    } else if (p.mask_bits <= 32)
         hipLaunchKernelGGL((k_cdc_roll<uint32_t, 0>), grid, block, 0, s, in, g.n, p.base,
                            p.b48, p.mask, l1, l2, cnt, (uint64_t *)nullptr, lgk);
     else

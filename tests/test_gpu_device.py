@@ -244,12 +244,17 @@ def _candidates(P, torch, data, params):
     return d, n, ws, ws_bytes, _np(cand[:k]).view(np.uint64)
 
 
+# masks of up to 15 bits roll two parts per lane in 16-bit halves, 16..32
+# bits in 32-bit registers, wider ones in 64-bit: the cases cover each side
+# of both switches
 @pytest.mark.parametrize("case", ["random13", "dense4", "none64", "zeros", "bits32",
-                                  "bits40", "tiny"])
+                                  "bits40", "tiny", "bits1", "bits15", "bits16", "bits17"])
 def test_candidates_vs_oracle(P, torch_cuda, case):
     base = gen.cdc_base()
     n, bits = 3 * (1 << 20) + 77, 13
     data = None
+    if case.startswith("bits") and case not in ("bits32", "bits40"):
+        bits = int(case[4:])
     if case == "dense4":
         bits = 4
     elif case == "none64":
@@ -270,6 +275,17 @@ def test_candidates_vs_oracle(P, torch_cuda, case):
     params = P.cdc_params(base, mask_bits=bits)
     *_, got = _candidates(P, torch_cuda, data, params)
     assert np.array_equal(got, oracle.candidates(data, base, bits))
+
+
+# short inputs: the last lane's first part is cut short and its second part
+# is short or empty (16 lanes per range, parts of 128 bytes)
+@pytest.mark.parametrize("n", [48, 129, 200, 300, 4097, 6001])
+def test_candidates_ragged_parts(P, torch_cuda, n):
+    base = gen.cdc_base()
+    data = gen.random_bytes(n + 7, n)
+    params = P.cdc_params(base, mask_bits=4)
+    *_, got = _candidates(P, torch_cuda, data, params)
+    assert np.array_equal(got, oracle.candidates(data, base, 4))
 
 
 # inputs whose range counts give the candidate launch 8, 4 and 2 lanes per
