@@ -625,6 +625,29 @@ __global__ __launch_bounds__(64) void k_sel_walk(SelArgs a)
     a.exit_[t] = s;
 }
 
+// Copy tile t's c starts to ends[o - 1 ...] (start number j >= 1 is end j-1;
+// entries past cap are dropped).  Eight loads are issued before their
+// stores, so a tile costs one or two memory round trips instead of c.
+__device__ __forceinline__ void emit_tile(const SelArgs &a, uint32_t t, uint32_t c, uint64_t o,
+                                          uint64_t *__restrict__ ends, uint64_t cap)
+{
+    const uint64_t *src = a.starts + (uint64_t)t * a.tile_cap;
+    if (c > a.tile_cap)
+        c = a.tile_cap; // cannot happen: starts in a tile lie min_len apart
+    for (uint32_t i = 0; i < c; i += 8) {
+        uint64_t v[8];
+#pragma unroll
+        for (uint32_t q = 0; q < 8; q++)
+            v[q] = i + q < c ? src[i + q] : 0;
+#pragma unroll
+        for (uint32_t q = 0; q < 8; q++) {
+            const uint64_t k = o + i + q;
+            if (i + q < c && k >= 1 && k - 1 < cap)
+                ends[k - 1] = v[q];
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_sel_verify(SelArgs a)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -662,14 +685,7 @@ __global__ __launch_bounds__(64) void k_sel_emit(SelArgs a, const uint64_t *__re
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.n_tiles)
         return;
-    const uint64_t o = toff[t];
-    const uint32_t c = a.tcnt[t];
-    const uint64_t *src = a.starts + (uint64_t)t * a.tile_cap;
-    for (uint32_t i = 0; i < c; i++) {
-        const uint64_t k = o + i;
-        if (k >= 1 && k - 1 < cap)
-            ends[k - 1] = src[i];
-    }
+    emit_tile(a, t, a.tcnt[t], toff[t], ends, cap);
     if (t == a.n_tiles - 1) {
         const uint64_t m = *total; // number of chunk starts = number of chunks
         if (m >= 1 && m - 1 < cap)
@@ -817,13 +833,7 @@ __global__ __launch_bounds__(1024) void k_sel_finish(SelArgs a, uint64_t *__rest
         total += wsum[k];
     }
     // start number j >= 1 is end j-1; the last end is n
-    const uint64_t o = before + x - c;
-    const uint64_t *src = a.starts + (uint64_t)t * a.tile_cap;
-    for (uint32_t i = 0; i < c; i++) {
-        const uint64_t k = o + i;
-        if (k >= 1 && k - 1 < cap)
-            ends[k - 1] = src[i];
-    }
+    emit_tile(a, t, c, before + x - c, ends, cap);
     const uint64_t m = total;
     if (t == 0) {
         if (m >= 1 && m - 1 < cap)

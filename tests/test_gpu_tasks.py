@@ -179,6 +179,30 @@ def test_concurrent_submitters(lib):
     assert len(seen) == 48
 
 
+def test_cdc_jobs_past_1024_tiles(P):
+    """Chunking jobs of 65 MiB + 5 bytes (1041 tiles) through the job layer:
+    past what one finishing workgroup takes, so selection and the chunk order
+    run as separate kernels inside the batch; one job alone, then two
+    submitted together."""
+    P.crystal_init(max_input_bytes=66 << 20, host_pool_bytes=512 << 20,
+                   device_pool_bytes=1 << 30, n_streams=2)
+    try:
+        base = gen.cdc_base()
+        params = P.cdc_params(base)
+        for batch in (1, 2):
+            datas = [gen.random_bytes(900 + 7 * batch + k, (65 << 20) + 5) for k in range(batch)]
+            subs = [_submit(P, P.K_CDC, d, params) for d in datas]
+            for (t, inb, outb), d in zip(subs, datas):
+                assert P.crystal_wait(t) == 0
+                ends, dig = P.parse_cdc_output(P.buffer_view(outb)[:t.out_bytes])
+                ee, ed = oracle.cdc(d, base)
+                assert np.array_equal(ends, ee) and np.array_equal(dig, ed)
+                P.crystal_buffer_release(inb)
+                P.crystal_buffer_release(outb)
+    finally:
+        P.crystal_finalize()
+
+
 def test_poll_timeout_and_busy_release(lib):
     P = lib
     data = gen.random_bytes(1, 64 << 20)
