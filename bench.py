@@ -158,6 +158,9 @@ def main() -> int:
                     help="batches whose roots one root launch computes (R)")
     ap.add_argument("--e2e-streams", type=int, default=2)
     ap.add_argument("--e2e-window", type=int, default=12)
+    ap.add_argument("--e2e-copy-streams", type=int, default=2,
+                    help="copy-in streams of the job layer in the host-fed leg (with the "
+                         "2 compute streams, one hardware queue each)")
     ap.add_argument("--cpu-jobs", type=int, default=0,
                     help="jobs in the CPU oracle sample (0 = sized to ~10 s)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -367,7 +370,8 @@ def main() -> int:
         window = args.e2e_window
         P.crystal_init(max_input_bytes=JOB_BYTES, host_pool_bytes=64 << 20,
                        device_pool_bytes=1 << 30, n_streams=args.e2e_streams,
-                       max_in_flight=max(16, 2 * window))
+                       max_in_flight=max(16, 2 * window),
+                       n_copy_streams=args.e2e_copy_streams)
         try:
             direct = P.crystal_direct_params(segment_bytes=SEGMENT)
             cap = P.crystal_output_bytes(P.K_MD5_DIRECT, JOB_BYTES, direct)
@@ -392,6 +396,7 @@ def main() -> int:
             e2e["pipelined_ok"] = int(best_run[2])
             e2e["pipelined_window"] = window
             e2e["pipelined_streams"] = args.e2e_streams
+            e2e["pipelined_copy_streams"] = args.e2e_copy_streams
             ok_roots = all(bytes(outs[j, cap - 16:].numpy()) == bytes(roots[j].cpu().numpy())
                            for j in (0, 77, 255))
             e2e["pipelined_matches_device_step"] = bool(ok_roots)

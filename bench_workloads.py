@@ -457,7 +457,7 @@ def chunking(P, torch, gen, reps=10):
 
 # --------------------------------------------------------------------- serving
 
-def serving(P, torch, gen, loads, n_jobs, n_streams=3, direct_frac=0.7):
+def serving(P, torch, gen, loads, n_jobs, n_streams=3, direct_frac=0.7, n_copy_streams=0):
     arena_bytes = 4 << 30
     arena = torch.empty(arena_bytes, dtype=torch.uint8).pin_memory()
     gen.fill(gen.sub_seed(gen.config_seed(4), 5), arena.data_ptr(), arena_bytes)
@@ -473,7 +473,8 @@ def serving(P, torch, gen, loads, n_jobs, n_streams=3, direct_frac=0.7):
     ooff[1:] = np.cumsum((caps[:-1] + 255) // 256 * 256)
     outs = torch.empty(int(ooff[-1] + caps[-1]), dtype=torch.uint8).pin_memory()
     P.crystal_init(max_input_bytes=64 << 20, host_pool_bytes=16 << 20,
-                   device_pool_bytes=16 << 30, n_streams=n_streams, max_in_flight=64)
+                   device_pool_bytes=16 << 30, n_streams=n_streams, max_in_flight=64,
+                   n_copy_streams=n_copy_streams)
     results = []
     try:
         for load in loads:
@@ -590,6 +591,8 @@ def main() -> int:
     ap.add_argument("--loads", default="5,10,20,30,40,45,50")
     ap.add_argument("--serving-jobs", type=int, default=0)
     ap.add_argument("--serving-streams", type=int, default=3)
+    ap.add_argument("--serving-copy-streams", type=int, default=0,
+                    help="copy-in streams of the job layer (0 = its default, 1)")
     ap.add_argument("--serving-direct-frac", type=float, default=0.7,
                     help="share of direct-hashing jobs in the serving mix (the rest chunk)")
     ap.add_argument("--batch-buffers", type=int, default=0)
@@ -642,7 +645,7 @@ def main() -> int:
     if want("serving"):
         loads = [float(x) for x in args.loads.split(",")]
         serving(P, torch, gen, loads, args.serving_jobs or (2000 if args.quick else 20000),
-                args.serving_streams, args.serving_direct_frac)
+                args.serving_streams, args.serving_direct_frac, args.serving_copy_streams)
     return 0
 
 

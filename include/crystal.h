@@ -105,16 +105,21 @@ typedef struct crystal_config {
                                  takes input, output and scratch; 0 = 8 *
                                  per-job need of the largest job */
     uint32_t n_streams;       /* compute streams jobs are spread over (each
-                                 also carries its jobs' copy-out); one more
-                                 stream carries every copy-in; 0 = 3 */
+                                 also carries its jobs' copy-out); 0 = 3 */
     uint32_t max_in_flight;   /* dispatched but unfinished jobs; 0 = 4*n_streams */
     int32_t device;           /* HIP device ordinal */
     uint32_t flags;           /* CRYSTAL_F_* */
     void *device_slab;        /* optional caller-owned device memory of
                                  device_pool_bytes (e.g. from PyTorch); the
                                  library then allocates no device pool itself */
-    void **streams;           /* optional caller-owned streams: n_streams + 1
-                                 entries, [0] = copy-in, [1..] = compute */
+    void **streams;           /* optional caller-owned streams:
+                                 n_copy_streams + n_streams entries, copy-in
+                                 streams first, then the compute streams */
+    uint32_t n_copy_streams;  /* copy-in streams that batches rotate over,
+                                 1..8; 0 = 2 if the library creates its
+                                 streams and n_streams + 2 fits the process's
+                                 hardware queues (GPU_MAX_HW_QUEUES, default
+                                 4), else 1 */
 } crystal_config;
 
 typedef struct crystal_buf crystal_buf; /* opaque pooled/wrapped host buffer */

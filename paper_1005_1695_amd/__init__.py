@@ -234,18 +234,19 @@ def batch_device(d_arena, offsets, lengths, order=None, block=256, grid=0,
 def crystal_init(max_input_bytes: int, max_output_bytes: int = 0,
                  host_pool_bytes: int = 0, device_pool_bytes: int = 0,
                  n_streams: int = 0, max_in_flight: int = 0, device: int = 0,
-                 device_slab=None, streams=None) -> None:
+                 device_slab=None, streams=None, n_copy_streams: int = 0) -> None:
     cfg = crystal_config(max_input_bytes=max_input_bytes,
                          max_output_bytes=max_output_bytes,
                          host_pool_bytes=host_pool_bytes,
                          device_pool_bytes=device_pool_bytes,
                          n_streams=n_streams, max_in_flight=max_in_flight,
                          device=device, flags=0,
-                         device_slab=_ptr(device_slab) or None)
+                         device_slab=_ptr(device_slab) or None,
+                         n_copy_streams=n_copy_streams)
     keep = None
-    if streams:  # [copy-in stream, compute streams...]
+    if streams:  # [copy-in streams (n_copy_streams, default 1), compute streams...]
         keep = (ctypes.c_void_p * len(streams))(*[_stream(s) for s in streams])
-        cfg.n_streams = len(streams) - 1
+        cfg.n_streams = len(streams) - (n_copy_streams or 1)
         cfg.streams = ctypes.cast(keep, ctypes.POINTER(ctypes.c_void_p))
     check(load().crystal_init(ctypes.byref(cfg)), "crystal_init")
 

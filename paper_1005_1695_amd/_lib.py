@@ -41,7 +41,8 @@ class crystal_config(ctypes.Structure):
                 ("host_pool_bytes", c_sz), ("device_pool_bytes", c_sz),
                 ("n_streams", c_u32), ("max_in_flight", c_u32),
                 ("device", c_i32), ("flags", c_u32),
-                ("device_slab", c_vp), ("streams", ctypes.POINTER(c_vp))]
+                ("device_slab", c_vp), ("streams", ctypes.POINTER(c_vp)),
+                ("n_copy_streams", c_u32)]
 
 
 class crystal_task(ctypes.Structure):

@@ -87,6 +87,16 @@ def test_calls_before_init_are_rejected(P):
     assert "not initialised" in P.last_error()
 
 
+def test_init_rejects_bad_stream_counts(P):
+    """Stream counts are checked before any device call."""
+    lib = P.load()
+    import ctypes
+    for kw in ({"n_streams": 65}, {"n_copy_streams": 9}):
+        cfg = P.crystal_config(max_input_bytes=1 << 20, **kw)
+        assert lib.crystal_init(ctypes.byref(cfg)) == P._lib.EINVAL
+        assert "must be <=" in P.last_error()
+
+
 def test_device_calls_validate_before_launch(P):
     lib = P.load()
     # segment size not a multiple of 64 -> EINVAL, no launch attempted

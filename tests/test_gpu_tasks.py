@@ -203,6 +203,57 @@ def test_cdc_jobs_past_1024_tiles(P):
         P.crystal_finalize()
 
 
+@pytest.mark.parametrize("layout", ["one_copy_stream", "three_copy_streams",
+                                    "default_with_2_compute",
+                                    "caller_streams_2_copy_2_compute"])
+def test_copy_stream_layouts(P, torch_cuda, layout):
+    """Jobs submitted together under each copy-in stream layout: batches
+    rotate over the copy-in streams, and every result equals the oracle's."""
+    torch = torch_cuda
+    keep = None
+    if layout == "one_copy_stream":
+        P.crystal_init(max_input_bytes=4 << 20, host_pool_bytes=128 << 20,
+                       device_pool_bytes=256 << 20, n_streams=2, n_copy_streams=1)
+    elif layout == "three_copy_streams":
+        P.crystal_init(max_input_bytes=4 << 20, host_pool_bytes=128 << 20,
+                       device_pool_bytes=256 << 20, n_streams=3, n_copy_streams=3)
+    elif layout == "default_with_2_compute":  # two copy-in streams fit the queues
+        P.crystal_init(max_input_bytes=4 << 20, host_pool_bytes=128 << 20,
+                       device_pool_bytes=256 << 20, n_streams=2)
+    else:
+        keep = [torch.cuda.Stream() for _ in range(4)]
+        P.crystal_init(max_input_bytes=4 << 20, host_pool_bytes=128 << 20,
+                       device_pool_bytes=256 << 20, streams=keep, n_copy_streams=2)
+    try:
+        base = gen.cdc_base()
+        subs = []
+        for k in range(12):
+            n = (1 << 20) + 4099 * k
+            data = gen.random_bytes(700 + k, n)
+            if k % 3 == 2:
+                subs.append((data, P.K_CDC) + _submit(P, P.K_CDC, data, P.cdc_params(base)))
+            else:
+                subs.append((data, P.K_MD5_DIRECT) + _submit(P, P.K_MD5_DIRECT, data))
+        streams_seen = set()
+        for data, kid, t, inb, outb in subs:
+            assert P.crystal_wait(t) == 0
+            streams_seen.add(t.stream_index)
+            out = P.buffer_view(outb)[:t.out_bytes]
+            if kid == P.K_CDC:
+                ends, dig = P.parse_cdc_output(out)
+                ee, ed = oracle.cdc(data, base)
+                assert np.array_equal(ends, ee) and np.array_equal(dig, ed)
+            else:
+                es, er = oracle.direct(data)
+                assert np.array_equal(out[:-16].reshape(-1, 16), es)
+                assert out[-16:].tobytes() == er
+            P.crystal_buffer_release(inb)
+            P.crystal_buffer_release(outb)
+        assert streams_seen <= set(range(3))
+    finally:
+        P.crystal_finalize()
+
+
 def test_poll_timeout_and_busy_release(lib):
     P = lib
     data = gen.random_bytes(1, 64 << 20)
