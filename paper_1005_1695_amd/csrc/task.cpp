@@ -188,6 +188,7 @@ struct Batch {
     std::vector<Job *> jobs;
     int stream = 0;
     int in_stream = 0; // copy-in stream
+    uint64_t est_us = 0; // estimated serial time on its compute stream
     hipEvent_t ev_in = nullptr, ev = nullptr;
     int slot = -1; // job-table slot
 };
@@ -210,6 +211,7 @@ struct Lib {
     std::vector<std::unique_ptr<std::condition_variable>> cv_stream;
     std::deque<Job *> outstanding;
     std::vector<std::deque<Batch *>> running;
+    std::vector<uint64_t> load_us; // per compute stream: sum of its running batches' est_us
     RangeAlloc dev_alloc, host_alloc;
     uint8_t *dev_slab = nullptr, *host_slab = nullptr;
     bool own_dev = false;
@@ -252,16 +254,54 @@ static void finish_task(Lib *L, crystal_task *t, int status)
     L->cv_done.notify_all();
 }
 
+// Serial time a batch holds its compute stream, in microseconds: its longest
+// chain at about 0.6 us per compression (a direct job's segment plus its root
+// over the segment digests; a chunking job's longest possible chunk; a
+// whole-message MD5), plus a few microseconds of launches per job.  A 64 MiB
+// direct job's root alone is 4097 compressions, about 2.5 ms.
+static uint64_t batch_est_us(const Batch *b)
+{
+    uint64_t chain = 0;
+    for (const Job *j : b->jobs) {
+        uint64_t c = 0;
+        switch (j->kernel) {
+        case CRYSTAL_K_MD5_DIRECT:
+        case CRYSTAL_K_SHA1_DIRECT: {
+            const uint64_t nseg = (j->n + j->seg_bytes - 1) / j->seg_bytes;
+            const uint64_t dig = j->kernel == CRYSTAL_K_MD5_DIRECT ? 16 : 20;
+            c = j->seg_bytes / 64 + 1 + dig * nseg / 64 + 1;
+            break;
+        }
+        case CRYSTAL_K_CDC:
+            c = (j->n < j->cp.max_len ? j->n : j->cp.max_len) / 64 + 1;
+            break;
+        case CRYSTAL_K_MD5:
+            c = j->n / 64 + 1;
+            break;
+        default:
+            break;
+        }
+        chain = std::max(chain, c);
+    }
+    return chain * 6 / 10 + 5 * b->jobs.size();
+}
+
+// The compute stream with the least estimated work queued (ties: fewer
+// batches, then round robin).  Counting batches alone sent small jobs behind
+// a large direct job's root chain, which holds its stream for milliseconds.
 static int pick_stream(Lib *L)
 {
     const int S = (int)L->streams.size();
     int best = -1;
+    uint64_t best_w = 0;
     size_t best_n = 0;
     for (int k = 0; k < S; k++) {
         const int s = (int)((L->rr + k) % S);
+        const uint64_t w = L->load_us[s];
         const size_t q = L->running[s].size();
-        if (best < 0 || q < best_n) {
+        if (best < 0 || w < best_w || (w == best_w && q < best_n)) {
             best = s;
+            best_w = w;
             best_n = q;
         }
     }
@@ -502,7 +542,9 @@ static void dispatcher_main(Lib *L)
             b->slot = L->free_slots.back();
             L->free_slots.pop_back();
         }
+        b->est_us = batch_est_us(b);
         b->stream = pick_stream(L);
+        L->load_us[b->stream] += b->est_us;
         b->in_stream = (int)(L->rr_in++ % L->streams_in.size());
         for (Job *j : b->jobs) {
             j->stream = b->stream;
@@ -519,6 +561,7 @@ static void dispatcher_main(Lib *L)
             (void)hipStreamSynchronize(L->streams[b->stream]);
             set_error(CRYSTAL_EDEVICE, "job enqueue: %s", hipGetErrorString(e));
             lk.lock();
+            L->load_us[b->stream] -= b->est_us;
             release_batch_resources(L, b);
             L->failed += b->jobs.size();
             lk.unlock();
@@ -570,6 +613,7 @@ static void completer_main(Lib *L, int s)
             set_error(CRYSTAL_EDEVICE, "job execution: %s", hipGetErrorString(e));
         lk.lock();
         L->running[s].pop_front();
+        L->load_us[s] -= b->est_us;
         release_batch_resources(L, b);
         for (size_t k = 0; k < b->jobs.size(); k++) {
             if (status[k] == CRYSTAL_OK) {
@@ -762,6 +806,7 @@ int crystal_init(const crystal_config *cfg_in)
     for (uint32_t i = 0; i < n_slots; i++)
         L->free_slots.push_back((int)i);
     L->running.resize(cfg.n_streams);
+    L->load_us.assign(cfg.n_streams, 0);
     for (uint32_t s = 0; s < cfg.n_streams; s++)
         L->cv_stream.emplace_back(new std::condition_variable);
     Lib *raw = L.release();
