@@ -181,8 +181,8 @@ def main() -> int:
                                   args.counters_out, args.counters_command)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(the workload is sharded by job across GPUs, which this build does "
-              "not run)", file=sys.stderr)
+              "(the workload would shard by job across GPUs; only the one-GPU "
+              "path is implemented)", file=sys.stderr)
         return 2
 
     import torch

@@ -13,8 +13,8 @@
  *     hashing with SHA-1 (20-byte segment digests, root over their
  *     concatenation) is the variant of the paper's own measurements
  *     (Sec. 5.2).  The paper's application is StoreGPU's hashing of a
- *     stream of data blocks (Sec. 2.2, Sec. 5.2); it measures SHA1 there, and
- *     this build fixes MD5 as the digest.
+ *     stream of data blocks (Sec. 2.2, Sec. 5.2); it measures SHA1 there,
+ *     and MD5 is the primary digest here.
  *   - Direct hashing: the "direct hashing" primitive of Sec. 5.2 (Fig. 6):
  *     digest every fixed-size segment, then the CPU post-processing stage
  *     digests the concatenated segment digests.  Segment size 4 KiB; a short
