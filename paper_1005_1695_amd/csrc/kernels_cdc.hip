@@ -160,70 +160,81 @@ __global__ __launch_bounds__(256) void k_cdc_roll_x2(const uint8_t *__restrict__
     roll16x2(w, pa2, pb2, zero, zero, B, nB48, M2);
     roll16x2(w, pa3, pb3, zero, zero, B, nB48, M2);
 
+    // 128 bytes of each part per step, loaded together, so that each
+    // 128-byte line is requested once and used at once (taking a line in
+    // two 64-byte halves a step apart let the cache evict it in between and
+    // fetch it twice: 1.36x the input)
     uint64_t l2bits = 0;
     uint32_t count = 0;
-    const uint32_t ngroups = (uint32_t)((a1 - a0 + 63) >> 6); // part B is never longer
-    uint4 ca0 = load_vec(in, a0, n), ca1 = load_vec(in, a0 + 16, n);
-    uint4 ca2 = load_vec(in, a0 + 32, n), ca3 = load_vec(in, a0 + 48, n);
-    uint4 cb0 = load_vec(in, b0, n), cb1 = load_vec(in, b0 + 16, n);
-    uint4 cb2 = load_vec(in, b0 + 32, n), cb3 = load_vec(in, b0 + 48, n);
-    for (uint32_t g = 0; g < ngroups; g++) {
-        const uint64_t pa = a0 + 64ull * g, pb = b0 + 64ull * g;
-        uint4 na0 = zero, na1 = zero, na2 = zero, na3 = zero;
-        uint4 nb0 = zero, nb1 = zero, nb2 = zero, nb3 = zero;
-        if (g + 1 < ngroups) {
-            na0 = load_vec(in, pa + 64, n);
-            na1 = load_vec(in, pa + 80, n);
-            na2 = load_vec(in, pa + 96, n);
-            na3 = load_vec(in, pa + 112, n);
-            nb0 = load_vec(in, pb + 64, n);
-            nb1 = load_vec(in, pb + 80, n);
-            nb2 = load_vec(in, pb + 96, n);
-            nb3 = load_vec(in, pb + 112, n);
+    const uint32_t nsteps = (uint32_t)((a1 - a0 + 127) >> 7); // part B is never longer
+    uint4 ca[8], cb[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        ca[k] = load_vec(in, a0 + 16 * k, n);
+        cb[k] = load_vec(in, b0 + 16 * k, n);
+    }
+    for (uint32_t g = 0; g < nsteps; g++) {
+        const uint64_t pa = a0 + 128ull * g, pb = b0 + 128ull * g;
+        uint4 na[8], nb[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            na[k] = nb[k] = zero;
+        if (g + 1 < nsteps) {
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                na[k] = load_vec(in, pa + 128 + 16 * k, n);
+                nb[k] = load_vec(in, pb + 128 + 16 * k, n);
+            }
         }
         // leaving bytes of vector q are those of the vector 48 bytes back
-        const uint32_t r0 = roll16x2(w, ca0, cb0, pa1, pb1, B, nB48, M2);
-        const uint32_t r1 = roll16x2(w, ca1, cb1, pa2, pb2, B, nB48, M2);
-        const uint32_t r2 = roll16x2(w, ca2, cb2, pa3, pb3, B, nB48, M2);
-        const uint32_t r3 = roll16x2(w, ca3, cb3, ca0, cb0, B, nB48, M2);
-        uint64_t wa = (uint64_t)((r0 & 0xffffu) | (r1 << 16)) |
-                      ((uint64_t)((r2 & 0xffffu) | (r3 << 16)) << 32);
-        uint64_t wb = (uint64_t)((r0 >> 16) | (r1 & 0xffff0000u)) |
-                      ((uint64_t)((r2 >> 16) | (r3 & 0xffff0000u)) << 32);
-        // positions below 47 have no full window; positions past a part's
-        // end are outside it (part B may end first, or be empty)
-        if (pa < 47)
-            wa &= ~0ull << (47 - pa);
-        if (pa + 64 > a1)
-            wa &= (1ull << (a1 - pa)) - 1; // pa < a1 here
-        if (pb >= b1)
-            wb = 0;
-        else if (pb + 64 > b1)
-            wb &= (1ull << (b1 - pb)) - 1;
-        if (wa) {
-            l1[pa >> 6] = wa;
-            l2bits |= 1ull << (ga + g);
-            count += __popcll(wa);
+        uint32_t r[8];
+        r[0] = roll16x2(w, ca[0], cb[0], pa1, pb1, B, nB48, M2);
+        r[1] = roll16x2(w, ca[1], cb[1], pa2, pb2, B, nB48, M2);
+        r[2] = roll16x2(w, ca[2], cb[2], pa3, pb3, B, nB48, M2);
+#pragma unroll
+        for (int q = 3; q < 8; q++)
+            r[q] = roll16x2(w, ca[q], cb[q], ca[q - 3], cb[q - 3], B, nB48, M2);
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            uint64_t wa = (uint64_t)((r[4 * h] & 0xffffu) | (r[4 * h + 1] << 16)) |
+                          ((uint64_t)((r[4 * h + 2] & 0xffffu) | (r[4 * h + 3] << 16)) << 32);
+            uint64_t wb = (uint64_t)((r[4 * h] >> 16) | (r[4 * h + 1] & 0xffff0000u)) |
+                          ((uint64_t)((r[4 * h + 2] >> 16) | (r[4 * h + 3] & 0xffff0000u)) << 32);
+            const uint64_t qa = pa + 64 * h, qb = pb + 64 * h;
+            // positions below 47 have no full window; positions past a
+            // part's end are outside it (part B may end first, or be empty)
+            if (qa < 47)
+                wa &= ~0ull << (47 - qa);
+            if (qa >= a1)
+                wa = 0;
+            else if (qa + 64 > a1)
+                wa &= (1ull << (a1 - qa)) - 1;
+            if (qb >= b1)
+                wb = 0;
+            else if (qb + 64 > b1)
+                wb &= (1ull << (b1 - qb)) - 1;
+            if (wa) {
+                l1[qa >> 6] = wa;
+                l2bits |= 1ull << (ga + 2 * g + h);
+                count += __popcll(wa);
+            }
+            if (wb) {
+                l1[qb >> 6] = wb;
+                l2bits |= 1ull << (gb + 2 * g + h);
+                count += __popcll(wb);
+            }
         }
-        if (wb) {
-            l1[pb >> 6] = wb;
-            l2bits |= 1ull << (gb + g);
-            count += __popcll(wb);
+        pa1 = ca[5];
+        pa2 = ca[6];
+        pa3 = ca[7];
+        pb1 = cb[5];
+        pb2 = cb[6];
+        pb3 = cb[7];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            ca[k] = na[k];
+            cb[k] = nb[k];
         }
-        pa1 = ca1;
-        pa2 = ca2;
-        pa3 = ca3;
-        ca0 = na0;
-        ca1 = na1;
-        ca2 = na2;
-        ca3 = na3;
-        pb1 = cb1;
-        pb2 = cb2;
-        pb3 = cb3;
-        cb0 = nb0;
-        cb1 = nb1;
-        cb2 = nb2;
-        cb3 = nb3;
     }
     for (uint32_t o = 1; o < (1u << lgk); o <<= 1) {
         l2bits |= __shfl_xor(l2bits, (int)o);
