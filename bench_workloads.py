@@ -457,7 +457,8 @@ def chunking(P, torch, gen, reps=10):
 
 # --------------------------------------------------------------------- serving
 
-def serving(P, torch, gen, loads, n_jobs, n_streams=3, direct_frac=0.7, n_copy_streams=0):
+def serving(P, torch, gen, loads, n_jobs, n_streams=3, direct_frac=0.7, n_copy_streams=0,
+            in_flight=64):
     arena_bytes = 4 << 30
     arena = torch.empty(arena_bytes, dtype=torch.uint8).pin_memory()
     gen.fill(gen.sub_seed(gen.config_seed(4), 5), arena.data_ptr(), arena_bytes)
@@ -473,7 +474,7 @@ def serving(P, torch, gen, loads, n_jobs, n_streams=3, direct_frac=0.7, n_copy_s
     ooff[1:] = np.cumsum((caps[:-1] + 255) // 256 * 256)
     outs = torch.empty(int(ooff[-1] + caps[-1]), dtype=torch.uint8).pin_memory()
     P.crystal_init(max_input_bytes=64 << 20, host_pool_bytes=16 << 20,
-                   device_pool_bytes=16 << 30, n_streams=n_streams, max_in_flight=64,
+                   device_pool_bytes=16 << 30, n_streams=n_streams, max_in_flight=in_flight,
                    n_copy_streams=n_copy_streams)
     results = []
     try:
@@ -515,7 +516,8 @@ def serving(P, torch, gen, loads, n_jobs, n_streams=3, direct_frac=0.7, n_copy_s
     return out("serving", {"points": results, "operating_point": op,
                            "mean_job_bytes": float(spec0["size"].mean()),
                            "direct_frac": direct_frac,
-                           "device_pool_gib": 16, "compute_streams": n_streams})
+                           "device_pool_gib": 16, "compute_streams": n_streams,
+                           "max_in_flight": in_flight})
 
 
 # ----------------------------------------------------------------------- batch
@@ -591,6 +593,8 @@ def main() -> int:
     ap.add_argument("--loads", default="5,10,20,30,40,45,50")
     ap.add_argument("--serving-jobs", type=int, default=0)
     ap.add_argument("--serving-streams", type=int, default=3)
+    ap.add_argument("--serving-in-flight", type=int, default=64,
+                    help="jobs dispatched but unfinished at once (the job layer's max_in_flight)")
     ap.add_argument("--serving-copy-streams", type=int, default=0,
                     help="copy-in streams of the job layer (0 = its default, 1)")
     ap.add_argument("--serving-direct-frac", type=float, default=0.7,
@@ -645,7 +649,8 @@ def main() -> int:
     if want("serving"):
         loads = [float(x) for x in args.loads.split(",")]
         serving(P, torch, gen, loads, args.serving_jobs or (2000 if args.quick else 20000),
-                args.serving_streams, args.serving_direct_frac, args.serving_copy_streams)
+                args.serving_streams, args.serving_direct_frac, args.serving_copy_streams,
+                args.serving_in_flight)
     return 0
 
 
