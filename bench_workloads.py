@@ -458,7 +458,7 @@ def chunking(P, torch, gen, reps=10):
 # --------------------------------------------------------------------- serving
 
 def serving(P, torch, gen, loads, n_jobs, n_streams=3, direct_frac=0.7, n_copy_streams=0,
-            in_flight=64):
+            in_flight=48):
     arena_bytes = 4 << 30
     arena = torch.empty(arena_bytes, dtype=torch.uint8).pin_memory()
     gen.fill(gen.sub_seed(gen.config_seed(4), 5), arena.data_ptr(), arena_bytes)
@@ -593,7 +593,7 @@ def main() -> int:
     ap.add_argument("--loads", default="5,10,20,30,40,45,50")
     ap.add_argument("--serving-jobs", type=int, default=0)
     ap.add_argument("--serving-streams", type=int, default=3)
-    ap.add_argument("--serving-in-flight", type=int, default=64,
+    ap.add_argument("--serving-in-flight", type=int, default=48,
                     help="jobs dispatched but unfinished at once (the job layer's max_in_flight)")
     ap.add_argument("--serving-copy-streams", type=int, default=0,
                     help="copy-in streams of the job layer (0 = its default, 1)")
