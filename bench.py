@@ -11,7 +11,7 @@ over the job's concatenated segment digests.
   layer overlaps consecutive batches: segment digests go to a ring of 3R
   batch slots, and one root launch computes the roots of R consecutive
   batches (R x 256 serial chains, on one of two root streams) while the
-  segment kernels of later batches run (--root-group R, default 4).  `value`
+  segment kernels of later batches run (--root-group R, default 5).  `value`
   is hashed GB/s (10^9 bytes/s) over the K timed steps (default 60), all of
   whose work (every segment digest and every root) completes inside the
   timed region, including the final root group that runs alone at the end.
@@ -154,7 +154,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--no-e2e", action="store_true", help="skip the host-fed legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--root-group", type=int, default=4,
+    ap.add_argument("--root-group", type=int, default=5,
                     help="batches whose roots one root launch computes (R)")
     ap.add_argument("--e2e-streams", type=int, default=2)
     ap.add_argument("--e2e-window", type=int, default=12)
