@@ -427,6 +427,23 @@ __global__ __launch_bounds__(256) void k_cdc_compact(const uint64_t *__restrict_
     }
 }
 
+// Chunk length classes of the longest-first chunk order (see "chunk order"
+// below); the selection's packing kernel counts them too.
+constexpr uint32_t kLenClasses = 64;
+
+// Class 0 holds the longest chunks (>= 63 KiB + 1 byte, also every longer
+// chunk when max_len exceeds 64 KiB), class 63 the shortest (<= 1 KiB).
+__device__ __forceinline__ uint32_t len_class(uint64_t len)
+{
+    const uint64_t c = len ? (len - 1) >> 10 : 0;
+    return kLenClasses - 1 - (uint32_t)(c < kLenClasses - 1 ? c : kLenClasses - 1);
+}
+
+__device__ __forceinline__ uint64_t chunk_len(const uint64_t *ends, uint64_t k)
+{
+    return ends[k] - (k ? ends[k - 1] : 0);
+}
+
 // -------------------------------------------------------------- selection
 
 struct SelArgs {
@@ -659,50 +676,112 @@ __device__ __forceinline__ void emit_tile(const SelArgs &a, uint32_t t, uint32_t
     }
 }
 
-__global__ __launch_bounds__(256) void k_sel_verify(SelArgs a)
-{
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0 || t >= a.n_tiles)
-        return;
-    const uint32_t badt = a.exit_[t - 1] != a.first[t];
-    a.flags[t] = badt;
-    if (badt)
-        atomicAdd(&a.bad[0], 1u);
-}
-
-// One thread re-walks, in order, every tile whose entry disagrees with the
-// true chain, then re-checks the next tile whenever a repaired exit moved.
-__global__ void k_sel_repair(SelArgs a)
-{
-    if (blockIdx.x != 0 || threadIdx.x != 0)
-        return;
-    if (a.bad[0] == 0)
-        return;
-    for (uint32_t t = 1; t < a.n_tiles; t++) {
-        const uint64_t entry = a.exit_[t - 1];
-        if (entry == a.first[t])
-            continue;
-        walk_tile(a, t, entry);
-    }
-}
-
-// Pack the starts: global start index k = toff[t] + i; start k >= 1 is end
-// k-1; the last end is n.
+// Pack tile t's starts into the ends array (start k >= 1 is end k-1; the
+// last end is n).  With `hist` given, also count the chunks (below hcap) per
+// length class, which the longest-first order needs: the chunk at a tile's
+// last start ends at the tile's exit, the true next start once verification
+// and repair are done.  A repair re-walks, in order, every tile whose entry
+// disagrees with the true chain, so a repaired exit that moved is checked
+// against the next tile in turn.
 __global__ __launch_bounds__(64) void k_sel_emit(SelArgs a, const uint64_t *__restrict__ toff,
                                                  const uint64_t *__restrict__ total,
                                                  uint64_t *__restrict__ n_chunks,
-                                                 uint64_t *__restrict__ ends, uint64_t cap)
+                                                 uint64_t *__restrict__ ends, uint64_t cap,
+                                                 uint32_t *__restrict__ hist, uint64_t hcap)
 {
+    __shared__ uint32_t h[kLenClasses]; // one entry per lane of the 64-lane group
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.n_tiles)
-        return;
-    emit_tile(a, t, a.tcnt[t], toff[t], ends, cap);
-    if (t == a.n_tiles - 1) {
-        const uint64_t m = *total; // number of chunk starts = number of chunks
-        if (m >= 1 && m - 1 < cap)
-            ends[m - 1] = a.n;
-        *n_chunks = m;
+    if (hist) {
+        h[threadIdx.x] = 0;
+        __syncthreads();
     }
+    if (t < a.n_tiles) {
+        const uint32_t c = a.tcnt[t];
+        const uint64_t o = toff[t];
+        emit_tile(a, t, c, o, ends, cap);
+        if (hist) {
+            const uint64_t *src = a.starts + (uint64_t)t * a.tile_cap;
+            const uint32_t cc = c < a.tile_cap ? c : a.tile_cap;
+            for (uint32_t i = 0; i < cc && o + i < hcap; i++) {
+                const uint64_t nx = i + 1 < cc ? src[i + 1] : a.exit_[t];
+                atomicAdd(&h[len_class(nx - src[i])], 1u);
+            }
+        }
+        if (t == a.n_tiles - 1) {
+            const uint64_t m = *total; // number of chunk starts = number of chunks
+            if (m >= 1 && m - 1 < cap)
+                ends[m - 1] = a.n;
+            *n_chunks = m;
+        }
+    }
+    if (hist) {
+        __syncthreads();
+        if (h[threadIdx.x])
+            atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+    }
+}
+
+// Past one finishing workgroup's tiles: verification, the serial repair and
+// the scan of the tiles' counts in one workgroup (and the zeroing of the
+// length-class counts k_sel_emit adds to), in place of four launches.
+// Verification reads the tiles strided (coalesced); the scan gives thread i
+// the tiles [i T, (i + 1) T).
+__global__ __launch_bounds__(1024) void k_sel_verify_scan(SelArgs a, uint64_t *__restrict__ toff,
+                                                          uint64_t *__restrict__ total,
+                                                          uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t s_bad;
+    __shared__ uint64_t wsum[16];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid == 0)
+        s_bad = 0;
+    if (hist && tid < kLenClasses)
+        hist[tid] = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    for (uint32_t u = tid; u < a.n_tiles; u += 1024)
+        bad += u >= 1 && a.exit_[u - 1] != a.first[u];
+    if (bad)
+        atomicAdd(&s_bad, bad);
+    __syncthreads();
+    if (s_bad) {
+        if (tid == 0) {
+            for (uint32_t u = 1; u < a.n_tiles; u++) {
+                const uint64_t entry = a.exit_[u - 1];
+                if (entry != a.first[u])
+                    walk_tile(a, u, entry);
+            }
+        }
+        __syncthreads();
+    }
+    const uint32_t T = (a.n_tiles + 1023) / 1024;
+    const uint32_t u0 = tid * T < a.n_tiles ? tid * T : a.n_tiles;
+    const uint32_t u1 = u0 + T < a.n_tiles ? u0 + T : a.n_tiles;
+    uint64_t c = 0;
+    for (uint32_t u = u0; u < u1; u++)
+        c += a.tcnt[u];
+    uint64_t x = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = __shfl_up(x, d, 64);
+        if (lane >= (uint32_t)d)
+            x += y;
+    }
+    if (lane == 63)
+        wsum[wv] = x;
+    __syncthreads();
+    uint64_t before = 0, tot = 0;
+    for (uint32_t k = 0; k < 16; k++) {
+        before += k < wv ? wsum[k] : 0;
+        tot += wsum[k];
+    }
+    uint64_t o = before + x - c;
+    for (uint32_t u = u0; u < u1; u++) {
+        toff[u] = o;
+        o += a.tcnt[u];
+    }
+    if (tid == 0)
+        *total = tot;
 }
 
 __global__ void k_store_zero_u64(uint64_t *p)
@@ -721,20 +800,6 @@ __global__ void k_store_zero_u64(uint64_t *p)
 // the longest 1025 compressions) that measured 0.66 ms against 1.0 ms in
 // index order.  Counting sort: class histogram, scan, scatter.
 
-constexpr uint32_t kLenClasses = 64;
-
-// Class 0 holds the longest chunks (>= 63 KiB + 1 byte, also every longer
-// chunk when max_len exceeds 64 KiB), class 63 the shortest (<= 1 KiB).
-__device__ __forceinline__ uint32_t len_class(uint64_t len)
-{
-    const uint64_t c = len ? (len - 1) >> 10 : 0;
-    return kLenClasses - 1 - (uint32_t)(c < kLenClasses - 1 ? c : kLenClasses - 1);
-}
-
-__device__ __forceinline__ uint64_t chunk_len(const uint64_t *ends, uint64_t k)
-{
-    return ends[k] - (k ? ends[k - 1] : 0);
-}
 
 // One chunk per lane; per-workgroup class counts in LDS, added to hist.
 __global__ __launch_bounds__(256) void k_chunk_hist(const uint64_t *__restrict__ ends,
@@ -962,20 +1027,26 @@ hipError_t launch_cdc_select(const CdcGeom &g, const CdcParams &p, uint8_t *ws,
         }
         return launch_chunk_order(g, ws, d_n_chunks, d_ends, cap, order, s);
     }
-    e = launch_zero_u32(a.bad, 2u, s);
-    if (e != hipSuccess)
-        return e;
+    // the packing kernel also counts the chunks per length class when the
+    // order is wanted
+    const uint64_t ocap = cap < g.ord_cap ? cap : g.ord_cap;
+    uint32_t *hist = order && ocap > 0 ? reinterpret_cast<uint32_t *>(ws + g.off_hist) : nullptr;
     hipLaunchKernelGGL(k_sel_walk, dim3(g.n_tiles), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(k_sel_verify, dim3(nblk(g.n_tiles, 256)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_sel_repair, dim3(1), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, a.tcnt, (uint64_t)g.n_tiles,
-                       toff, total);
+    hipLaunchKernelGGL(k_sel_verify_scan, dim3(1), dim3(1024), 0, s, a, toff, total, hist);
     hipLaunchKernelGGL(k_sel_emit, dim3(nblk(g.n_tiles, 64)), dim3(64), 0, s, a, toff, total,
-                       d_n_chunks, d_ends, cap);
+                       d_n_chunks, d_ends, cap, hist, ocap);
     e = hipGetLastError();
-    if (e != hipSuccess || !order)
+    if (e != hipSuccess || !hist)
         return e;
-    return launch_chunk_order(g, ws, d_n_chunks, d_ends, cap, order, s);
+    uint32_t *cursor = hist + kLenClasses;
+    uint32_t *ord = reinterpret_cast<uint32_t *>(ws + g.off_ord);
+    hipLaunchKernelGGL(k_chunk_class_scan, dim3(1), dim3(64), 0, s, hist, cursor);
+    hipLaunchKernelGGL(k_chunk_scatter, dim3(nblk(ocap, 256)), dim3(256), 0, s, d_ends,
+                       d_n_chunks, ocap, cursor, ord);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+        *order = ord;
+    return e;
 }
 
 hipError_t launch_chunk_order(const CdcGeom &g, uint8_t *ws, const uint64_t *d_n_chunks,
