@@ -19,11 +19,12 @@
 //    start past it (its exit).  Two chains that reach the same start agree
 //    from then on, so if the exit of tile t-1 equals the first start tile t
 //    recorded, tile t's starts are exact; tile 0 starts at 0 and is exact.
-//    A verification pass checks every tile in parallel; tiles that fail are
-//    re-walked from the true entry by a repair pass (rare on real data).
-//    A scan of per-tile counts then packs the starts into the ends array.
-//    Inputs of up to 1024 tiles do all of this after the walk, and the
-//    chunk order, in one workgroup.
+//    Verification checks every tile; tiles that fail are re-walked from the
+//    true entry by a repair pass (rare on real data).  A scan of per-tile
+//    counts then packs the starts into the ends array.  Inputs of up to 1024
+//    tiles do all of this after the walk, and the chunk order, in one
+//    workgroup; larger ones verify, repair and scan in one workgroup and
+//    pack (counting the chunks' length classes for the order) in parallel.
 #include "internal.h"
 
 namespace crystal {
